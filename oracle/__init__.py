@@ -1,0 +1,165 @@
+"""FP64 CPU reference solver — test infrastructure only.
+
+Thin ctypes front-end over ``liboracle.so`` (built from ``oracle.cpp``).  Only the
+test-suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py`` may
+import this package; the GPU library never calls it and shares no code with it.
+
+The oracle follows FLUPS (arXiv 2211.07777): per-axis transforms chosen by the
+boundary conditions (Table I, Sec. II-B), domain doubling for unbounded directions and
+padding plus DCT/DST for semi-unbounded ones (Sec. II-C), multiplication by the Green's
+spectrum (Eq. of Sec. II) or by the Green's spectrum times the spectral curl (Sec. V).
+
+Boundary codes: 0 even, 1 odd, 2 periodic, 3 unbounded.  Layout: 0 cell, 1 node.
+Green: 0 CHAT2 as printed in Sec. IV (sphere-mean self-term times the cell volume),
+1 the sphere-mean self-term itself.  Kind: 0 Poisson, 1 Biot-Savart (spectral curl).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SRC_PATH = os.path.join(_HERE, "oracle.cpp")
+
+EVEN, ODD, PER, UNB = 0, 1, 2, 3
+CELL, NODE = 0, 1
+FAST, NAIVE, DIRECT = 0, 1, 2
+# FFTW-numbered real-to-real kinds
+REDFT00, REDFT01, REDFT10, REDFT11, RODFT00, RODFT01, RODFT10, RODFT11 = range(8)
+CLASS_NAMES = ["P", "EE", "OO", "EO", "OE", "UU", "EU", "OU", "UE", "UO"]
+
+
+def build(force: bool = False) -> str:
+    """Compile liboracle.so with g++ (OpenMP, FP64)."""
+    if force or not os.path.exists(_LIB_PATH) or (
+        os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC_PATH)
+    ):
+        cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-shared", "-fPIC", "-o", _LIB_PATH + ".tmp", _SRC_PATH]
+        subprocess.check_call(cmd)
+        os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        L.oracle_fft.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int]
+        L.oracle_dft_naive.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int]
+        L.oracle_r2r.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_int]
+        L.oracle_axis_info.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, ip]
+        L.oracle_green_value.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.oracle_green_value.restype = ctypes.c_double
+        L.oracle_solve.argtypes = [ip, dp, ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp]
+        L.oracle_green_spectrum.argtypes = [ip, dp, ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
+        L.oracle_spectral_dims.argtypes = [ip, dp, ip, ctypes.c_int, ip]
+        L.oracle_num_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def _check(rc):
+    if rc != 0:
+        raise ValueError(f"oracle error {rc}")
+
+
+def fft(x, sign=-1):
+    x = np.ascontiguousarray(x, dtype=np.complex128)
+    y = np.empty_like(x)
+    _check(lib().oracle_fft(x.size, _dp(x.view(np.float64)), _dp(y.view(np.float64)), sign))
+    return y
+
+
+def dft_naive(x, sign=-1):
+    x = np.ascontiguousarray(x, dtype=np.complex128)
+    y = np.empty_like(x)
+    _check(lib().oracle_dft_naive(x.size, _dp(x.view(np.float64)), _dp(y.view(np.float64)), sign))
+    return y
+
+
+def r2r(kind, x, naive=False):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.empty_like(x)
+    _check(lib().oracle_r2r(kind, x.size, _dp(x), _dp(y), 1 if naive else 0))
+    return y
+
+
+def axis_info(N, h, node, bl, br):
+    info = np.zeros(12, dtype=np.int32)
+    _check(lib().oracle_axis_info(N, h, node, bl, br, _ip(info)))
+    keys = ["cls", "nuser", "nspec", "nlog", "fwd", "bwd", "first", "kshift", "unb", "dft", "rev", "half2"]
+    d = dict(zip(keys, (int(v) for v in info)))
+    d["cls_name"] = CLASS_NAMES[d["cls"]]
+    return d
+
+
+def green_value(du, variant, cellvol, rho, k):
+    return lib().oracle_green_value(du, variant, cellvol, rho, k)
+
+
+def _prep(n, h, bc):
+    n = np.ascontiguousarray(n, dtype=np.int32)
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    bc = np.ascontiguousarray(np.asarray(bc).reshape(-1), dtype=np.int32)
+    assert n.size == 3 and h.size == 3 and bc.size == 6
+    return n, h, bc
+
+
+def user_shape(n, layout):
+    """(nz, ny, nx) of the user's array."""
+    add = 1 if layout == NODE else 0
+    return (int(n[2]) + add, int(n[1]) + add, int(n[0]) + add)
+
+
+def solve(rhs, n, h, bc, layout, green=0, kind=0, mode=FAST):
+    """Solve lap(u) = f (kind 0) or lap(u) = curl(f) (kind 1).
+
+    rhs: array [nz, ny, nx] (Poisson) or [3, nz, ny, nx] (Biot-Savart), FP64.
+    n: intervals (node) or cells (cell) per axis (x, y, z); h: spacing per axis;
+    bc: [[xl, xr], [yl, yr], [zl, zr]].
+    """
+    n, h, bc = _prep(n, h, bc)
+    shp = user_shape(n, layout)
+    ncomp = 3 if kind == 1 else 1
+    rhs = np.ascontiguousarray(rhs, dtype=np.float64).reshape((ncomp,) + shp)
+    out = np.empty_like(rhs)
+    _check(lib().oracle_solve(_ip(n), _dp(h), _ip(bc), layout, green, kind, mode, _dp(rhs), _dp(out)))
+    return out if kind == 1 else out[0]
+
+
+def spectral_dims(n, h, bc, layout):
+    n, h, bc = _prep(n, h, bc)
+    d = np.zeros(3, dtype=np.int32)
+    _check(lib().oracle_spectral_dims(_ip(n), _dp(h), _ip(bc), layout, _ip(d)))
+    return tuple(int(v) for v in d)  # (x, y, z)
+
+
+def green_spectrum(n, h, bc, layout, green=0, mode=FAST):
+    """Green's spectrum (with quadrature weight and 1/prod(nlog)), array [sz][sy][sx]."""
+    n, h, bc = _prep(n, h, bc)
+    dx, dy, dz = spectral_dims(n, h, bc, layout)
+    out = np.empty((dz, dy, dx), dtype=np.complex128)
+    _check(lib().oracle_green_spectrum(_ip(n), _dp(h), _ip(bc), layout, green, mode, _dp(out.view(np.float64))))
+    return out
+
+
+def num_threads():
+    return lib().oracle_num_threads()
