@@ -1,0 +1,197 @@
+#!/usr/bin/env python3
+"""Benchmark of the Fourier-convolution Poisson / Biot-Savart solve on one MI355X.
+
+A step is one whole solve (all five passes: first-axis forward, second-axis forward,
+fused last-axis forward + Green's-spectrum multiply + inverse, and the two inverse
+passes) of one synthetic right-hand side already resident in HBM.  Plans (twiddles and
+the Green's spectrum) are built before the timed region, as a user keeps them cached.
+
+Default workload: node-centred 128 x 128 x 256 intervals (arrays 129 x 129 x 257),
+x periodic, y even / odd, z unbounded, 8 seeded Gaussian bumps, FP32 (headline value)
+and FP64, each result compared with the FP64 oracle.
+
+Prints ONE JSON line.  --gpus above 1 is not supported (single-GPU library).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "mixed_node_128x128x256": dict(
+        desc="node-centred 128x128x256 (arrays 129x129x257), x periodic, y even/odd, z unbounded, "
+             "Poisson, 8 seeded Gaussian bumps",
+        n=[128, 128, 256], h=[1 / 128] * 3, bc=[[2, 2], [0, 1], [3, 3]], layout=1, kind=0),
+    "unbounded_cell_32": dict(
+        desc="cell-centred 32^3 on [-1,1]^3, fully unbounded, Poisson, Gaussian blob",
+        n=[32] * 3, h=[1 / 16] * 3, bc=[[3, 3]] * 3, layout=0, kind=0),
+    "biot_savart_ring_256": dict(
+        desc="cell-centred 256^3 on [-1,1]^3, fully unbounded, Biot-Savart (spectral curl), "
+             "vortex ring R=0.5 core 0.05 with seeded axial perturbation, 3 components",
+        n=[256] * 3, h=[2 / 256] * 3, bc=[[3, 3]] * 3, layout=0, kind=1),
+    "biot_savart_tubes_512": dict(
+        desc="cell-centred 512^3 on [-1,1]^3 (padded to 1024^3), fully unbounded, Biot-Savart, "
+             "16 seeded vortex rings, 3 components",
+        n=[512] * 3, h=[2 / 512] * 3, bc=[[3, 3]] * 3, layout=0, kind=1),
+    "unbounded_cell_512": dict(
+        desc="cell-centred 512^3 on [-1,1]^3 (padded to 1024^3), fully unbounded, scalar Poisson, "
+             "Gaussian blob",
+        n=[512] * 3, h=[2 / 512] * 3, bc=[[3, 3]] * 3, layout=0, kind=0),
+}
+
+
+def make_input(name):
+    from paper_2211_07777_amd import workloads as W
+    w = WORKLOADS[name]
+    if name == "mixed_node_128x128x256":
+        coords = [np.arange(w["n"][a] + 1) * w["h"][a] for a in range(3)]
+        return W.gaussian_bumps(coords, [1.0, 1.0, 2.0])
+    if name == "unbounded_cell_32":
+        return W.gaussian_blob(32)[0]
+    if name == "biot_savart_ring_256":
+        return W.vortex_ring(256)[0]
+    if name == "biot_savart_tubes_512":
+        return W.vortex_tubes(512)[0]
+    if name == "unbounded_cell_512":
+        return W.gaussian_blob(512, sigma=0.1)[0]
+    raise KeyError(name)
+
+
+def run_gpu(name, f64, prec, steps, warmup):
+    import torch
+    import paper_2211_07777_amd as F
+    w = WORKLOADS[name]
+    ncomp = 3 if w["kind"] == 1 else 1
+    plan = F.Plan(w["n"], w["h"], w["bc"], w["layout"], F.CHAT2, prec, w["kind"], ncomp)
+    info = F.plan_inspect(w["n"], w["h"], w["bc"], w["layout"], F.CHAT2, prec, w["kind"], ncomp)
+    rhs = torch.from_numpy(f64).to(device="cuda", dtype=plan.dtype).reshape(plan.shape).contiguous()
+    out = torch.empty_like(rhs)
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
+    for _ in range(warmup):
+        plan.solve(rhs, out, ws)
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        for p in range(5):
+            evs[k][p].record()
+            plan.solve_passes(rhs, out, p, p, ws)
+        evs[k][5].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / steps
+    pass_ms = np.array([[evs[k][p].elapsed_time(evs[k][p + 1]) for p in range(5)] for k in range(steps)])
+    gpu_step_ms = float(np.median(pass_ms.sum(axis=1)))
+    result = out.double().cpu().numpy()
+    plan.close()
+    return dict(ms_step=ms_step, pass_ms=pass_ms.mean(axis=0).tolist(), gpu_step_ms=gpu_step_ms,
+                info=info, result=result)
+
+
+def oracle_baseline(name, f64, budget_s=20.0):
+    import oracle
+    w = WORKLOADS[name]
+    t0 = time.perf_counter()
+    ref = oracle.solve(f64, w["n"], w["h"], w["bc"], w["layout"], 0, w["kind"])
+    first = time.perf_counter() - t0
+    reps, total = 1, first
+    while total + first < budget_s and reps < 5:
+        t0 = time.perf_counter()
+        oracle.solve(f64, w["n"], w["h"], w["bc"], w["layout"], 0, w["kind"])
+        total += time.perf_counter() - t0
+        reps += 1
+    return ref, total / reps, reps, oracle.num_threads()
+
+
+def load_traffic(name, kernel_pass):
+    """HBM bytes per launch of the dominant pass from the committed rocprofv3 counter
+    summary (profiles/), or None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{name}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    return d.get("bytes_per_launch", {}).get(str(kernel_pass))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="mixed_node_128x128x256", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this library runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2211_07777_amd as F
+
+    name = args.workload
+    w = WORKLOADS[name]
+    f64 = make_input(name)
+    ncomp = 3 if w["kind"] == 1 else 1
+    user_pts = float(np.prod([n + (1 if w["layout"] == 1 else 0) for n in w["n"]]))
+    r32 = run_gpu(name, f64, F.F32, args.steps, args.warmup)
+    r64 = run_gpu(name, f64, F.F64, args.steps, args.warmup)
+
+    cpu = None
+    err32 = err64 = None
+    if not args.no_cpu:
+        ref, cpu_s, reps, cores = oracle_baseline(name, f64)
+        scale = np.abs(ref).max()
+        err32 = float(np.abs(r32["result"] - ref).max() / scale)
+        err64 = float(np.abs(r64["result"] - ref).max() / scale)
+        cpu = {"value": user_pts * ncomp / cpu_s / 1e6, "unit": "Mpts/s", "cores": int(cores),
+               "kind": "oracle",
+               "sample": f"{reps} full FP64 oracle solve(s) of the same workload, {cpu_s:.2f} s each"}
+
+    mpts32 = user_pts * ncomp / (r32["ms_step"] * 1e-3) / 1e6
+    mpts64 = user_pts * ncomp / (r64["ms_step"] * 1e-3) / 1e6
+    dom = int(np.argmax(r32["pass_ms"]))
+    algo = r32["info"]["algo_bytes"][dom]
+    achieved = algo / (r32["pass_ms"][dom] * 1e-3) / 1e9
+    traffic = load_traffic(name, dom)
+    step_bytes = sum(r32["info"]["algo_bytes"])
+    line = {
+        "metric": "unbounded Poisson Mpts/s & solves/s, FP32 vs FP64; serving p50/p99 latency",
+        "value": mpts32,
+        "unit": "Mpts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["ms_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": name, "description": w["desc"], "points": int(user_pts), "components": ncomp,
+                   "precision_of_value": "fp32"},
+        "solves_per_s": 1e3 / r32["ms_step"],
+        "fp64": {"value": mpts64, "ms_per_step": r64["ms_step"], "solves_per_s": 1e3 / r64["ms_step"],
+                 "rel_linf_vs_oracle": err64},
+        "fp32_rel_linf_vs_oracle": err32,
+        "pass_ms_fp32": r32["pass_ms"],
+        "pass_ms_fp64": r64["pass_ms"],
+        "effective_GBps_fp32": step_bytes / (r32["gpu_step_ms"] * 1e-3) / 1e9,
+        "roofline": {"bound": "hbm", "kernel": f"pass {dom + 1} (pass_kernel<float>)", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

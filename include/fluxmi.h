@@ -1,0 +1,162 @@
+/*
+ * fluxmi — Fourier-convolution Poisson and Biot-Savart solver for one AMD MI355X
+ * (gfx950), after the FLUPS method (Balty, Chatelain, Gillis, arXiv 2211.07777).
+ *
+ * The solve computes u = G * f (Poisson, lap(u) = f; Eq. of Sec. II) or
+ * u = G * curl(f) (Biot-Savart, lap(u) = curl(f); Sec. V) on a uniform 3-D grid whose
+ * six faces each carry one boundary condition: even, odd (Sec. II-B, Table I),
+ * periodic (Sec. II-B) or unbounded (Sec. II-C; with a symmetric face opposite it the
+ * direction is semi-unbounded).  Each solve zero-pads unbounded directions (domain
+ * doubling), runs per-axis DFT / DCT / DST passes chosen from the boundary
+ * conditions, multiplies by a cached Green's spectrum (optionally through a spectral
+ * curl) and runs the inverse passes.
+ *
+ * Conventions shared by every entry point
+ *   - All functions use the C ABI, never throw, and return an int status:
+ *     FM_OK (0) or one of the negative FM_E_* codes below.
+ *   - Device pointers are plain HIP device addresses (e.g. from a torch tensor's
+ *     data_ptr()); `hip_stream` is a hipStream_t passed as void* (NULL = the null
+ *     stream).  All device work is stream-ordered; no entry point synchronises the
+ *     host with the device except fm_plan_create, which waits for the Green's spectrum.
+ *   - Arrays are contiguous, row-major, x fastest: [ncomp][nz][ny][nx] where n_a is
+ *     N_a cells (cell-centred: x_j = (j + 1/2) h) or N_a + 1 nodes (node-centred:
+ *     x_j = j h), Sec. II-A.  Element type double (FM_F64) or float (FM_F32).
+ *   - Axis a spans L_a = N_a * h_a.  Face order is (x-left, x-right, y-left, ...).
+ */
+#ifndef FLUXMI_H
+#define FLUXMI_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Boundary condition of one face (Sec. II-B, II-C). */
+typedef enum { FM_BC_EVEN = 0, FM_BC_ODD = 1, FM_BC_PER = 2, FM_BC_UNB = 3 } fm_bc;
+
+/* Data layout (Sec. II-A). */
+typedef enum { FM_CELL = 0, FM_NODE = 1 } fm_layout;
+
+/* Green's function (Sec. IV names the CHAT2 kernel; its singular value at the origin
+ * is not printed in the paper):
+ *   FM_GREEN_CHAT2     -1/(4 pi r) with the origin value equal to the mean over the
+ *                      equal-volume sphere times the cell volume (the reading that
+ *                      reproduces the CHAT2 errors printed in Sec. IV);
+ *   FM_GREEN_CHAT2_VOL the same kernel with the plain equal-volume-sphere mean.
+ * With two convolution directions both use, at the origin, the square-cell mean of
+ * ln(rho)/(2 pi) (footnote of Sec. V) for the zero spectral wavenumber and the disc
+ * mean of -K0(k rho)/(2 pi) otherwise. */
+typedef enum { FM_GREEN_CHAT2 = 0, FM_GREEN_CHAT2_VOL = 1 } fm_green;
+
+/* Arithmetic of the transforms.  FM_F32 plans take their twiddles and Green's
+ * spectrum from FP64 evaluations rounded once to FP32. */
+typedef enum { FM_F64 = 0, FM_F32 = 1 } fm_prec;
+
+/* Poisson: lap(u) = f.  Biot-Savart: lap(u) = curl(f) with the curl taken in
+ * spectral space as i*omega x f_hat (Sec. V); needs periodic or fully unbounded
+ * conditions on every axis and ncomp = 3. */
+typedef enum { FM_POISSON = 0, FM_BIOT_SAVART = 1 } fm_kind;
+
+/* Status codes. */
+#define FM_OK 0
+#define FM_E_NULL (-1)   /* a required pointer is NULL                                */
+#define FM_E_BC (-2)     /* periodic on one face only, or an unknown code             */
+#define FM_E_SIZE (-3)   /* N < 2, h <= 0, or an FFT length with a prime factor > 7
+                            or longer than 4096                                       */
+#define FM_E_KIND (-4)   /* unknown kind / green / precision / layout, or Biot-Savart
+                            with ncomp != 3 or a symmetric / semi-unbounded axis      */
+#define FM_E_NOMEM (-5)  /* device allocation failed                                 */
+#define FM_E_HIP (-6)    /* a HIP call failed; fm_last_hip_error() has its code      */
+#define FM_E_ARG (-7)    /* inconsistent arguments (count, workspace too small, ...) */
+
+typedef struct fm_plan_s* fm_plan;
+
+/* Create a plan: classifies every axis (Table I and Sec. II-C), orders the axes by
+ * transform cost (symmetric, semi-unbounded, periodic, unbounded; Sec. I), sizes the
+ * padded transforms, and builds the twiddle tables and the Green's spectrum in FP64
+ * on the device (once per plan).
+ *   out       receives the plan (set to NULL on failure)
+ *   n[3]      N per axis (x, y, z): cells, or intervals for node-centred data
+ *   h[3]      grid spacing per axis
+ *   bc[3][2]  per-axis (left, right) face conditions
+ *   ncomp     independent right-hand sides per solve (Poisson), 3 for Biot-Savart
+ *   hip_stream  stream on which the spectrum is generated (synchronised on return)
+ * The plan owns its device memory (spectrum, twiddles, internal workspace). */
+int fm_plan_create(fm_plan* out, const int n[3], const double h[3], const int bc[3][2],
+                   int layout, int green, int prec, int kind, int ncomp, void* hip_stream);
+
+/* Release a plan and its device memory.  The caller must make sure no solve that
+ * uses it is still in flight.  NULL is accepted and ignored. */
+int fm_plan_destroy(fm_plan p);
+
+/* Bytes of device workspace a solve with this plan needs (2 spectral buffers per
+ * component, sized for the padded volumes). */
+int fm_plan_workspace_bytes(fm_plan p, size_t* bytes);
+
+/* The user array extents (nx, ny, nz): N or N + 1 per axis. */
+int fm_plan_shape(fm_plan p, int user_dims[3]);
+
+/* Solve for one set of right-hand sides.
+ *   rhs_dev   [ncomp][nz][ny][nx] input, never written
+ *   out_dev   same shape; may alias rhs_dev (in-place mode)
+ *   workspace_dev  at least fm_plan_workspace_bytes bytes, or NULL to use the plan's
+ *             own workspace (then concurrent solves with one plan must not overlap)
+ * Output conventions: nodes on an odd face are exactly 0; the node-centred periodic
+ * duplicate f_N equals f_0; input values at those positions are ignored. */
+int fm_solve(fm_plan p, const void* rhs_dev, void* out_dev, void* workspace_dev, void* hip_stream);
+
+/* Run passes [first_pass, last_pass] (0-based, of the five: 0 first-axis forward,
+ * 1 second-axis forward, 2 last-axis forward + spectral multiply + inverse,
+ * 3 second-axis inverse, 4 first-axis inverse) of fm_solve with the same arguments.
+ * Running 0..4 in one or several calls, in order on one stream, equals fm_solve; the
+ * workspace carries the intermediate results between calls, so it must be passed
+ * explicitly (NULL selects the plan's own workspace). */
+int fm_solve_passes(fm_plan p, const void* rhs_dev, void* out_dev, void* workspace_dev,
+                    int first_pass, int last_pass, void* hip_stream);
+
+/* Solve `count` independent problems (plans may differ in shape, boundary conditions
+ * and layout, but must share one precision) with one launch per pass for the whole
+ * batch.  Each result is bitwise identical to fm_solve of the same plan.
+ *   workspace_dev  at least fm_batched_workspace_bytes(count, plans) bytes */
+int fm_solve_batched(int count, const fm_plan* plans, const void* const* rhs_dev,
+                     void* const* out_dev, void* workspace_dev, size_t workspace_bytes,
+                     void* hip_stream);
+
+/* Workspace for fm_solve_batched: the sum over plans of fm_plan_workspace_bytes,
+ * each rounded up to 256 bytes, plus the batch's descriptor table. */
+int fm_batched_workspace_bytes(int count, const fm_plan* plans, size_t* bytes);
+
+/* Planning information, available without a device (host-only arithmetic). */
+typedef struct {
+  int order[3];         /* transform order, as axis indices (0 x, 1 y, 2 z)           */
+  int axis_class[3];    /* per axis x, y, z: 0 P, 1 EE, 2 OO, 3 EO, 4 OE, 5 UU, 6 EU,
+                           7 OU, 8 UE, 9 UO (left face first)                          */
+  int fft_len[3];       /* FFT length used along each axis                           */
+  int spec_len[3];      /* extent of each axis after its forward transform           */
+  int green_dims[3];    /* Green table extents, in transform order                   */
+  size_t workspace_bytes;
+  int tiles[5];         /* workgroups of the five passes                             */
+  int lines_per_tile[5];
+  int lds_bytes[5];
+  double algo_bytes[5]; /* bytes each pass must move (reads + writes of the live
+                           volumes, zero padding never read, the Green's spectrum read
+                           once by the fused pass), all components                          */
+} fm_plan_info;
+
+/* Run the planner of fm_plan_create (classification, order, sizes, layouts, tiles and
+ * the bounds check of every pass) without touching a device.  Same arguments and
+ * status codes as fm_plan_create; nothing is allocated. */
+int fm_plan_inspect(const int n[3], const double h[3], const int bc[3][2], int layout, int green,
+                    int prec, int kind, int ncomp, fm_plan_info* info);
+
+/* Human-readable text for a status code (static storage). */
+const char* fm_error_string(int status);
+
+/* The last HIP error code seen by this library in the calling thread (0 if none). */
+int fm_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FLUXMI_H */

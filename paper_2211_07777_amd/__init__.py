@@ -1,0 +1,10 @@
+"""fluxmi: Fourier-convolution Poisson / Biot-Savart solver for AMD MI355X (gfx950).
+
+The compute path is the HIP library ``libfluxmi.so`` (C ABI, ``include/fluxmi.h``);
+this package only marshals arguments (torch tensors for device memory and streams).
+"""
+from .fluxmi import (  # noqa: F401
+    CELL, NODE, EVEN, ODD, PER, UNB, F64, F32, POISSON, BIOT_SAVART, CHAT2, CHAT2_VOL,
+    FluxmiError, Plan, plan_inspect, solve_batched, batched_workspace_bytes, library,
+    error_string,
+)

@@ -1,0 +1,107 @@
+// Descriptor of one "line pass": a batch of 1-D transforms along one axis of a 3-D
+// array, read from one layout and written (transposed) into another.  Shared by the
+// host planner and the device kernels of the GPU library.
+#pragma once
+#include <stdint.h>
+
+namespace fm {
+
+constexpr int kThreads = 256;    // threads per workgroup of every pass kernel
+constexpr int kElems = 16;       // complex values per thread held across a radix stage
+constexpr int kMaxLen = 4096;    // longest FFT
+constexpr int kMaxStages = 16;
+constexpr int kMaxLds = 163840;  // LDS a gfx950 workgroup may allocate
+constexpr int kSoftLds = 65536;  // preferred tile LDS (keeps >= 2 workgroups per CU)
+
+// How the FFT input z[0..M) of one FFT line is built from the loaded tile.
+enum Gather : int32_t {
+  G_CPLX = 0,   // z[m] = x[m] for m < n_data, else 0                      (complex lines)
+  G_REAL2 = 1,  // z[m] = x1[m] + i x2[m] for m < n_data, else 0          (2 real lines)
+  G_HERM2 = 2,  // z[m] = X1[m] + i X2[m] from two Hermitian half-spectra (inverse R2C)
+  G_R2R = 3,    // symmetric extension of 2 real lines, pre-twiddle        (DCT / DST)
+};
+
+// How the FFT output Z[0..M) becomes the written line(s).
+enum Scatter : int32_t {
+  S_CPLX = 0,   // y[j] = Z[j mod M]                                      (complex lines)
+  S_R2C2 = 1,   // two half-spectra X1[k], X2[k], k = 0..M/2                (forward R2C)
+  S_REAL2 = 2,  // y1[j] = Re Z[j mod M], y2[j] = Im Z[j mod M]             (inverse R2C)
+  S_R2R = 3,    // post-twiddle, real or imaginary part                    (DCT / DST)
+};
+
+// Real-to-real transform in the form  y_q = sum_p w_p x_p cs(pi (p+a)(q+b) / nh),
+// evaluated as a length-2nh DFT of a symmetric extension with pre- and post-twiddles.
+struct R2R {
+  int32_t nh;        // half period (FFT length M = 2 nh)
+  int32_t a2, b2;    // 2a, 2b (0 or 1)
+  int32_t sin;       // 0: cosine transform, 1: sine transform
+  int32_t plo, phi;  // input index range (inclusive)
+  int32_t wlo, whi;  // weights of the end points (2 elsewhere)
+  int32_t in_rev, in_base;   // line index j of input p: rev ? base - p : p - base
+  int32_t qlo, qhi;  // output index range (inclusive); others write 0
+  int32_t out_rev, out_base; // output index q of line index j: rev ? base - j : j + base
+};
+
+// Green's spectrum lookup (pass 3).  Table index along an axis: DFT axes fold the
+// mode index k to min(k, M - k); real-to-real axes use the spectral index itself.
+struct GreenRef {
+  const void* G;       // table [F_c][F_b][F_line] in the working precision
+  int32_t F_b, F_line; // table extents along the tile axis and the line axis
+  int32_t fold_c, fold_b, fold_line;  // 0: identity, else the DFT length M to fold with
+  // spectral curl (Biot-Savart): wavenumber of mode k on DFT axis = 2 pi k' / period
+  int32_t curl;
+  int32_t axis_line, axis_b, axis_c;  // physical axis (0 x, 1 y, 2 z) of each direction
+  double dw_line, dw_b, dw_c;         // 2 pi / period
+  int32_t M_line, M_b, M_c;           // DFT lengths for the signed-mode map
+};
+
+// Output conventions applied by the last pass along its two batch axes (Sec. II-A,
+// II-B): node-centred periodic duplicate f_N := f_0, nodes on odd faces := 0.
+struct Fixup {
+  int32_t b_dup, b_zero_lo, b_zero_hi, b_last;
+  int32_t c_dup, c_zero_lo, c_zero_hi, c_last;
+};
+
+struct PassDesc {
+  // tile geometry: lines along `line`, B consecutive lines along `b`, index c, comp
+  const void* in;
+  void* out;
+  int64_t in_s_line, in_s_b, in_s_c, in_s_comp;    // element strides of the input
+  int64_t out_s_line, out_s_b, out_s_c, out_s_comp; // element strides of the output
+  int32_t nb, nc, ncomp;    // extents of b, c and the component count
+  int32_t in_n, out_n;      // values read / written per line
+  int32_t in_cplx, out_cplx;
+  int32_t B;                // lines per tile
+  int32_t tiles;            // tiles of this pass = ceil(nb / B) * nc * (ncomp or 1)
+  // transform
+  int32_t M;
+  int32_t nstages;
+  int32_t radix[kMaxStages];
+  const void* tw;           // 4M table: tw[j] = exp(-2 pi i j / (4M))
+  int32_t gather, scatter;
+  int32_t n_data;           // G_CPLX / G_REAL2: values taken before the zero padding
+  R2R r2r;
+  // fused pass 3: forward (gather/scatter above with sign -1), spectral multiply,
+  // inverse (gather2/scatter2 with sign +1)
+  int32_t fused;            // 0: plain pass, 1: fused pass
+  int32_t sign;             // plain pass: -1 forward, +1 inverse
+  int32_t gather2, scatter2;
+  int32_t spec_n;           // fused R2R: spectral values per line held in LDS
+  R2R r2r2;
+  GreenRef g;
+  Fixup fix;                // last pass only
+  int32_t has_fix;
+  int32_t lds_bytes;        // dynamic LDS the tile needs
+};
+
+// Sampling description of the Green's function for the spectrum generation (FP64).
+struct GreenGen {
+  int32_t du, variant;       // convolution directions, self-term variant
+  double cellvol, r_eq;      // product of h over convolution directions, r_eq
+  int32_t unb[3];            // per table axis: 1 convolution direction, 0 spectral
+  double h[3];               // spacing (convolution directions)
+  double dw[3], shift[3];    // spectral: omega = dw * (index + shift)
+  int32_t n[3];              // sample extents
+};
+
+}  // namespace fm

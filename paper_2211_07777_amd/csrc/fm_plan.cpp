@@ -1,0 +1,981 @@
+// Host side of the GPU library: planning (boundary conditions -> per-axis transforms,
+// transform order, padded sizes, data layouts, tile shapes), generation of twiddles and
+// of the Green's spectrum on the device, and the C entry points of include/fluxmi.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "../../include/fluxmi.h"
+#include "fm_pass.h"
+
+namespace fm {
+template <typename T> hipError_t launch_pass(const PassDesc& d, hipStream_t st);
+template <typename T>
+hipError_t launch_pass_batched(const PassDesc* ds, const int* prefix, int n, int total_tiles,
+                               int lds_bytes, hipStream_t st);
+template <typename T> hipError_t launch_twiddles(void* out, int M, hipStream_t st);
+
+hipError_t launch_green_sample(double* S, const GreenGen& g, hipStream_t st);
+template <typename T>
+hipError_t launch_green_final(void* G, const double* S, const int F[3], const int n[3],
+                              const int off[3], double scale, hipStream_t st);
+}  // namespace fm
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+#define FM_HIP(call)                       \
+  do {                                     \
+    hipError_t e_ = (call);                \
+    if (e_ != hipSuccess) {                \
+      g_last_hip = (int)e_;                \
+      return FM_E_HIP;                     \
+    }                                      \
+  } while (0)
+
+// per-axis class (left/right faces)
+enum Cls { C_P, C_EE, C_OO, C_EO, C_OE, C_UU, C_EU, C_OU, C_UE, C_UO };
+
+// Real-to-real transform families (FFTW's numbering of the kinds).
+enum Kind { REDFT00, REDFT01, REDFT10, REDFT11, RODFT00, RODFT01, RODFT10, RODFT11 };
+
+// y_q = sum_p w_p x_p cs(pi (p + a)(q + b) / nh): parameters of each kind for n points
+// (input index t = p - pin, output index k = q - qout).
+struct KindForm {
+  int nh_add, a2, b2, sin, pin, wlo, whi, qout;
+};
+KindForm kind_form(int k) {
+  switch (k) {
+    case REDFT00: return {-1, 0, 0, 0, 0, 1, 1, 0};
+    case RODFT00: return {+1, 0, 0, 1, 1, 2, 2, 1};
+    case REDFT10: return {0, 1, 0, 0, 0, 2, 2, 0};
+    case REDFT01: return {0, 0, 1, 0, 0, 1, 2, 0};
+    case REDFT11: return {0, 1, 1, 0, 0, 2, 2, 0};
+    case RODFT10: return {0, 1, 0, 1, 0, 2, 2, 1};
+    case RODFT01: return {0, 0, 1, 1, 1, 2, 1, 0};
+    default: return {0, 1, 1, 1, 0, 2, 2, 0};  // RODFT11
+  }
+}
+
+struct AxisPlan {
+  int N = 0, nuser = 0, cls = C_P;
+  double h = 0, L = 0;
+  bool node = false, unb = false, dft = false, rev = false;
+  // DFT axes
+  int M = 0, n_data = 0;
+  bool first_dft = false;
+  // real-to-real axes
+  int fwd = 0, bwd = 0, first = 0, nin = 0;
+  int nspec = 0;          // spectral extent along this axis after its forward pass
+  double nlog = 1;        // normalisation length
+  // Green table
+  int F = 0, Fs = 0, off = 0;
+  double dw = 0, shift = 0;
+};
+
+int classify(int bl, int br, int* cls) {
+  if (bl < 0 || bl > 3 || br < 0 || br > 3) return FM_E_BC;
+  if ((bl == FM_BC_PER) != (br == FM_BC_PER)) return FM_E_BC;
+  static const int table[4][4] = {
+      // right: EVEN  ODD   PER  UNB        left:
+      {C_EE, C_EO, -1, C_EU},  // EVEN
+      {C_OE, C_OO, -1, C_OU},  // ODD
+      {-1, -1, C_P, -1},       // PER
+      {C_UE, C_UO, -1, C_UU},  // UNB
+  };
+  *cls = table[bl][br];
+  return FM_OK;
+}
+
+// Table I (symmetric classes), Sec. II-B (periodic), Sec. II-C (unbounded and
+// semi-unbounded): forward / backward transforms, used input points, sizes.
+int plan_axis(int N, double h, bool node, int bl, int br, AxisPlan* a) {
+  if (N < 2 || !(h > 0)) return FM_E_SIZE;
+  int rc = classify(bl, br, &a->cls);
+  if (rc) return rc;
+  a->N = N;
+  a->h = h;
+  a->L = N * h;
+  a->node = node;
+  a->nuser = node ? N + 1 : N;
+  const int c = a->cls;
+  a->unb = c >= C_UU;
+  a->dft = (c == C_P || c == C_UU);
+  a->rev = (c == C_UE || c == C_UO);
+  if (c == C_P) {
+    a->M = N;
+    a->n_data = N;  // the node f_N duplicates f_0 and is not used
+    a->nlog = N;
+  } else if (c == C_UU) {
+    a->M = 2 * N;
+    a->n_data = a->nuser;  // zero padding up to 2N
+    a->nlog = 2 * N;
+  } else if (c <= C_OE) {
+    // spectral symmetric classes
+    if (node) {
+      switch (c) {
+        case C_EE: a->fwd = a->bwd = REDFT00; a->first = 0; a->nin = N + 1; break;
+        case C_OO: a->fwd = a->bwd = RODFT00; a->first = 1; a->nin = N - 1; break;
+        case C_OE: a->fwd = RODFT01; a->bwd = RODFT10; a->first = 1; a->nin = N; break;
+        default: a->fwd = REDFT01; a->bwd = REDFT10; a->first = 0; a->nin = N; break;  // EO
+      }
+    } else {
+      a->first = 0;
+      a->nin = N;
+      switch (c) {
+        case C_EE: a->fwd = REDFT10; a->bwd = REDFT01; break;
+        case C_OO: a->fwd = RODFT10; a->bwd = RODFT01; break;
+        case C_OE: a->fwd = a->bwd = RODFT11; break;
+        default: a->fwd = a->bwd = REDFT11; break;  // EO
+      }
+    }
+    a->nlog = 2 * N;
+  } else {
+    // semi-unbounded: padded to 2L on the unbounded side, DCT / DST on the extension
+    const bool even = (c == C_EU || c == C_UE);
+    if (node) {
+      if (even) { a->fwd = a->bwd = REDFT00; a->first = 0; a->nin = 2 * N + 1; }
+      else { a->fwd = a->bwd = RODFT00; a->first = 1; a->nin = 2 * N - 1; }
+    } else {
+      a->first = 0;
+      a->nin = 2 * N;
+      if (even) { a->fwd = REDFT10; a->bwd = REDFT01; }
+      else { a->fwd = RODFT10; a->bwd = RODFT01; }
+    }
+    a->nlog = 4 * N;
+  }
+  if (!a->dft) {
+    const KindForm f = kind_form(a->fwd);
+    a->M = 2 * (a->nin + f.nh_add);
+    a->nspec = a->nin;
+  }
+  return FM_OK;
+}
+
+// R2R descriptor of kind `k` with n points, mapped onto the line arrays.
+//  forward (dir = +1): input = user line (nuser, `first`, reversal), output = spectrum
+//  backward (dir = -1): input = spectrum, output = user line
+fm::R2R make_r2r(const AxisPlan& a, int kind, bool forward) {
+  const KindForm f = kind_form(kind);
+  const int n = a.nin;
+  fm::R2R r{};
+  r.nh = n + f.nh_add;
+  r.a2 = f.a2;
+  r.b2 = f.b2;
+  r.sin = f.sin;
+  r.plo = f.pin;
+  r.phi = f.pin + n - 1;
+  r.wlo = f.wlo;
+  r.whi = f.whi;
+  r.qlo = f.qout;
+  r.qhi = f.qout + n - 1;
+  if (forward) {
+    // p = (rev ? nuser-1-j : j) - first + pin
+    if (a.rev) { r.in_rev = 1; r.in_base = a.nuser - 1 - a.first + f.pin; }
+    else { r.in_rev = 0; r.in_base = f.pin - a.first; }
+    r.out_rev = 0;
+    r.out_base = f.qout;  // q = s + qout
+  } else {
+    r.in_rev = 0;
+    r.in_base = f.pin;    // p = s + pin
+    // q = (rev ? nuser-1-j : j) - first + qout
+    if (a.rev) { r.out_rev = 1; r.out_base = a.nuser - 1 - a.first + f.qout; }
+    else { r.out_rev = 0; r.out_base = f.qout - a.first; }
+  }
+  return r;
+}
+
+int radix_plan(int M, fm::PassDesc* d) {
+  if (M < 2 || M > fm::kMaxLen) return FM_E_SIZE;
+  int m = M, ns = 0;
+  const int rs[] = {8, 4, 2, 3, 5, 7};
+  for (int r : rs) {
+    while (m % r == 0) {
+      if (ns >= fm::kMaxStages) return FM_E_SIZE;
+      d->radix[ns++] = r;
+      m /= r;
+    }
+  }
+  if (m != 1) return FM_E_SIZE;
+  d->M = M;
+  d->nstages = ns;
+  return FM_OK;
+}
+
+// strides (elements) of a layout given its axis order (slow -> fast) and extents
+void layout_strides(const int order[3], const int ext[3], int64_t stride[3], int64_t* size) {
+  int64_t s = 1;
+  for (int i = 2; i >= 0; --i) {
+    stride[order[i]] = s;
+    s *= ext[order[i]];
+  }
+  *size = s;
+}
+
+}  // namespace
+
+struct fm_plan_s {
+  int n[3];
+  double h[3];
+  int bc[3][2];
+  int layout, green, prec, kind, ncomp;
+  AxisPlan ax[3];
+  int order[3];     // transform order
+  int tb1;          // tile axis of passes 1 and 5
+  int L1[3], L2[3]; // layouts (slow -> fast)
+  int ext_user[3], ext1[3], ext2[3];
+  int64_t Vu, V1, V2;
+  bool cplx1, cplx2;
+  size_t elem;      // sizeof(real)
+  size_t bytesA, bytesB;  // per component
+  size_t ws_bytes;
+  fm::PassDesc pass[5];
+  void* G = nullptr;
+  int GF[3];
+  std::map<int, void*> tw;
+  std::map<int, void*> tw64;
+  void* ws_internal = nullptr;
+  int device = 0;
+};
+
+namespace {
+
+size_t round256(size_t x) { return (x + 255) & ~size_t(255); }
+bool pass_in_bounds(const fm::PassDesc& d, int64_t in_size, int64_t out_size, size_t elem);
+
+// Largest tile (lines per workgroup) that fits the register budget and, if possible,
+// the preferred LDS size; otherwise the largest that fits the device's LDS.
+int choose_tile(fm::PassDesc* d, size_t elem, int comps, bool fused_r2r, int nb) {
+  const int packs = (d->gather == fm::G_CPLX) ? 1 : 2;
+  const size_t cplx = 2 * elem;
+  const size_t in_elem = d->in_cplx ? cplx : elem;
+  for (const int cap : {fm::kSoftLds, fm::kMaxLds}) {
+    int best = 0;
+    size_t best_lds = 0;
+    for (int B = 1; B <= 64; ++B) {
+      const int F = comps * ((B + packs - 1) / packs);
+      if ((int64_t)F * d->M > (int64_t)fm::kThreads * fm::kElems) break;
+      const size_t fft = (size_t)F * (d->M + 1) * cplx;
+      const size_t raw = (size_t)comps * B * (d->in_n + 1) * in_elem;
+      size_t lds = std::max(fft, raw);
+      if (fused_r2r) lds = std::max(lds, fft + (size_t)B * (d->spec_n + 1) * elem);
+      if (round256(lds) > (size_t)cap) break;
+      best = B;
+      best_lds = lds;
+      if (B >= nb) break;
+    }
+    if (best > 0) {
+      d->B = best;
+      d->lds_bytes = (int)round256(best_lds);
+      return FM_OK;
+    }
+  }
+  return FM_E_SIZE;
+}
+
+// Fill the geometry of a pass: lines along `la`, tiles along `lb`, index `lc`.
+void set_geometry(fm::PassDesc* d, int la, int lb, int lc, const int64_t sin_[3], int64_t in_size,
+                  const int64_t sout[3], int64_t out_size, const int ext_b[3]) {
+  d->in_s_line = sin_[la];
+  d->in_s_b = sin_[lb];
+  d->in_s_c = sin_[lc];
+  d->in_s_comp = in_size;
+  d->out_s_line = sout[la];
+  d->out_s_b = sout[lb];
+  d->out_s_c = sout[lc];
+  d->out_s_comp = out_size;
+  d->nb = ext_b[lb];
+  d->nc = ext_b[lc];
+}
+
+void set_transform(fm::PassDesc* d, const AxisPlan& a, bool forward, bool fused_half) {
+  (void)fused_half;
+  if (!a.dft) {
+    d->gather = fm::G_R2R;
+    d->scatter = fm::S_R2R;
+    d->sign = -1;
+    d->r2r = make_r2r(a, forward ? a.fwd : a.bwd, forward);
+    d->in_cplx = d->out_cplx = 0;
+    return;
+  }
+  if (a.first_dft) {
+    if (forward) {
+      d->gather = fm::G_REAL2;
+      d->scatter = fm::S_R2C2;
+      d->sign = -1;
+      d->n_data = a.n_data;
+      d->in_cplx = 0;
+      d->out_cplx = 1;
+    } else {
+      d->gather = fm::G_HERM2;
+      d->scatter = fm::S_REAL2;
+      d->sign = +1;
+      d->in_cplx = 1;
+      d->out_cplx = 0;
+    }
+  } else {
+    d->gather = fm::G_CPLX;
+    d->scatter = fm::S_CPLX;
+    d->sign = forward ? -1 : +1;
+    d->n_data = forward ? a.n_data : a.M;
+    d->in_cplx = d->out_cplx = 1;
+  }
+}
+
+template <typename T>
+int make_tables_and_green(fm_plan_s* p, hipStream_t st) {
+  // twiddle tables for every FFT length of the passes
+  for (int i = 0; i < 5; ++i) {
+    const int M = p->pass[i].M;
+    if (p->tw.count(M)) continue;
+    void* ptr = nullptr;
+    if (hipMalloc(&ptr, sizeof(T) * 2 * 4 * (size_t)M) != hipSuccess) return FM_E_NOMEM;
+    p->tw[M] = ptr;
+    FM_HIP(fm::launch_twiddles<T>(ptr, M, st));
+  }
+  for (int i = 0; i < 5; ++i) p->pass[i].tw = p->tw[p->pass[i].M];
+
+  // Green's spectrum: sample (FP64) -> DCT-I along convolution directions -> scale
+  const int* o = p->order;  // table axes = (a0, a1, a2), slow -> fast
+  fm::GreenGen g{};
+  int du = 0;
+  double vol = 1.0, scale = 1.0;
+  int Fs[3], F[3], off[3];
+  for (int i = 0; i < 3; ++i) {
+    const AxisPlan& a = p->ax[o[i]];
+    Fs[i] = a.Fs;
+    F[i] = a.F;
+    off[i] = a.off;
+    g.n[i] = a.Fs;
+    g.unb[i] = a.unb ? 1 : 0;
+    g.h[i] = a.h;
+    g.dw[i] = a.dw;
+    g.shift[i] = a.shift;
+    if (a.unb) {
+      du++;
+      vol *= a.h;
+      scale *= a.h;
+    }
+    scale /= a.nlog;
+  }
+  g.du = du;
+  g.variant = p->green;
+  g.cellvol = vol;
+  if (du == 3) g.r_eq = std::cbrt(3.0 * vol / (4.0 * M_PI));
+  if (du == 2) g.r_eq = std::sqrt(vol / M_PI);
+  const int64_t ns = (int64_t)Fs[0] * Fs[1] * Fs[2];
+  double* S = nullptr;
+  if (hipMalloc(&S, sizeof(double) * ns) != hipSuccess) return FM_E_NOMEM;
+  int rc = FM_OK;
+  FM_HIP(fm::launch_green_sample(S, g, st));
+  int64_t sstr[3] = {(int64_t)Fs[1] * Fs[2], Fs[2], 1};
+  for (int i = 0; i < 3 && rc == FM_OK; ++i) {
+    if (!g.unb[i]) continue;
+    // DCT-I (REDFT00) of Fs[i] samples, in place along table axis i
+    fm::PassDesc d{};
+    const int n = Fs[i];
+    const KindForm f = kind_form(REDFT00);
+    fm::R2R r{};
+    r.nh = n - 1; r.a2 = 0; r.b2 = 0; r.sin = 0;
+    r.plo = 0; r.phi = n - 1; r.wlo = f.wlo; r.whi = f.whi;
+    r.in_rev = 0; r.in_base = 0; r.qlo = 0; r.qhi = n - 1; r.out_rev = 0; r.out_base = 0;
+    d.r2r = r;
+    d.gather = fm::G_R2R;
+    d.scatter = fm::S_R2R;
+    d.sign = -1;
+    if ((rc = radix_plan(2 * (n - 1), &d))) break;
+    const int lb = (i == 2) ? 1 : 2;  // tile along the fastest other axis
+    const int lc = 3 - i - lb;
+    d.in = S;
+    d.out = S;
+    d.in_s_line = d.out_s_line = sstr[i];
+    d.in_s_b = d.out_s_b = sstr[lb];
+    d.in_s_c = d.out_s_c = sstr[lc];
+    d.in_s_comp = d.out_s_comp = 0;
+    d.nb = Fs[lb];
+    d.nc = Fs[lc];
+    d.ncomp = 1;
+    d.in_n = d.out_n = n;
+    if ((rc = choose_tile(&d, sizeof(double), 1, false, d.nb))) break;
+    d.tiles = ((d.nb + d.B - 1) / d.B) * d.nc;
+    if (!pass_in_bounds(d, ns, ns, sizeof(double))) { rc = FM_E_SIZE; break; }
+    void* t64 = nullptr;
+    auto it = p->tw64.find(d.M);
+    if (it == p->tw64.end()) {
+      if (hipMalloc(&t64, sizeof(double) * 2 * 4 * (size_t)d.M) != hipSuccess) { rc = FM_E_NOMEM; break; }
+      p->tw64[d.M] = t64;
+      FM_HIP(fm::launch_twiddles<double>(t64, d.M, st));
+    } else {
+      t64 = it->second;
+    }
+    d.tw = t64;
+    FM_HIP(fm::launch_pass<double>(d, st));
+  }
+  if (rc == FM_OK) {
+    const int64_t nG = (int64_t)F[0] * F[1] * F[2];
+    if (hipMalloc(&p->G, sizeof(T) * nG) != hipSuccess) rc = FM_E_NOMEM;
+    else FM_HIP(fm::launch_green_final<T>(p->G, S, F, Fs, off, scale, st));
+  }
+  hipError_t e = hipStreamSynchronize(st);
+  (void)hipFree(S);
+  for (auto& kv : p->tw64) (void)hipFree(kv.second);
+  p->tw64.clear();
+  if (rc) return rc;
+  if (e != hipSuccess) { g_last_hip = (int)e; return FM_E_HIP; }
+  for (int i = 0; i < 3; ++i) p->GF[i] = F[i];
+  return FM_OK;
+}
+
+void free_plan(fm_plan_s* p) {
+  if (!p) return;
+  for (auto& kv : p->tw) (void)hipFree(kv.second);
+  for (auto& kv : p->tw64) (void)hipFree(kv.second);
+  if (p->G) (void)hipFree(p->G);
+  if (p->ws_internal) (void)hipFree(p->ws_internal);
+  delete p;
+}
+
+// Host-side check of one pass against the buffers and the LDS / register budgets; the
+// index ranges mirror what the tile kernels touch.
+bool pass_in_bounds(const fm::PassDesc& d, int64_t in_size, int64_t out_size, size_t elem) {
+  auto span = [](int nc, int64_t sc, int nb, int64_t sb, int n, int64_t sl) {
+    return (int64_t)(nc - 1) * sc + (int64_t)(nb - 1) * sb + (int64_t)(n - 1) * sl;
+  };
+  if (d.nb < 1 || d.nc < 1 || d.in_n < 1 || d.out_n < 1 || d.B < 1) return false;
+  if (span(d.nc, d.in_s_c, d.nb, d.in_s_b, d.in_n, d.in_s_line) >= in_size) return false;
+  if (span(d.nc, d.out_s_c, d.nb, d.out_s_b, d.out_n, d.out_s_line) >= out_size) return false;
+  if (d.has_fix) {
+    const int bl = d.fix.b_dup ? std::max(d.nb, d.fix.b_last + 1) : d.nb;
+    const int cl = d.fix.c_dup ? std::max(d.nc, d.fix.c_last + 1) : d.nc;
+    if (span(cl, d.out_s_c, bl, d.out_s_b, d.out_n, d.out_s_line) >= out_size) return false;
+    if (d.fused || d.out_cplx) return false;  // applied by the real-output last pass only
+  }
+  if (d.in_s_comp < in_size && d.ncomp > 1 && !(d.fused && d.g.curl && d.ncomp == 3)) return false;
+  const int M = d.M;
+  int prodR = 1;
+  for (int i = 0; i < d.nstages; ++i) prodR *= d.radix[i];
+  if (prodR != M || M < 2 || M > fm::kMaxLen) return false;
+  auto r2r_ok = [&](const fm::R2R& r) { return 2 * r.nh == M && r.qhi < M && r.qlo >= 0 && r.plo >= 0 && r.phi <= r.nh; };
+  switch (d.gather) {
+    case fm::G_CPLX: case fm::G_REAL2: if (d.n_data > d.in_n || d.n_data > M) return false; break;
+    case fm::G_HERM2: if (d.in_n < M / 2 + 1) return false; break;
+    case fm::G_R2R: if (!r2r_ok(d.r2r)) return false; break;
+    default: return false;
+  }
+  if (!d.fused) {
+    switch (d.scatter) {
+      case fm::S_CPLX: case fm::S_REAL2: if (d.out_n > 2 * M) return false; break;
+      case fm::S_R2C2: if (d.out_n > M / 2 + 1) return false; break;
+      case fm::S_R2R: if (!r2r_ok(d.r2r)) return false; break;
+      default: return false;
+    }
+  } else {
+    if (d.gather == fm::G_R2R && (!r2r_ok(d.r2r2) || d.spec_n < 1)) return false;
+    if (d.gather != fm::G_R2R && d.out_n > 2 * M) return false;
+    if (d.g.curl && d.gather != fm::G_CPLX) return false;
+  }
+  const int comps = (d.fused && d.g.curl) ? 3 : 1;
+  const int packs = (d.gather == fm::G_CPLX) ? 1 : 2;
+  const int F = comps * ((d.B + packs - 1) / packs);
+  if ((int64_t)F * M > (int64_t)fm::kThreads * fm::kElems) return false;
+  const size_t fft = (size_t)F * (M + 1) * 2 * elem;
+  const size_t raw = (size_t)comps * d.B * (d.in_n + 1) * (d.in_cplx ? 2 : 1) * elem;
+  size_t need = std::max(fft, raw);
+  if (d.fused && d.gather == fm::G_R2R) need = std::max(need, fft + (size_t)d.B * (d.spec_n + 1) * elem);
+  if (need > (size_t)d.lds_bytes || d.lds_bytes > fm::kMaxLds) return false;
+  const int nbt = (d.nb + d.B - 1) / d.B;
+  if (d.tiles != nbt * d.nc * (comps == 3 ? 1 : d.ncomp)) return false;
+  return true;
+}
+
+int build_plan(fm_plan_s* p) {
+  const bool node = p->layout == FM_NODE;
+  for (int a = 0; a < 3; ++a) {
+    const int rc = plan_axis(p->n[a], p->h[a], node, p->bc[a][0], p->bc[a][1], &p->ax[a]);
+    if (rc) return rc;
+  }
+  if (p->kind == FM_BIOT_SAVART) {
+    if (p->ncomp != 3) return FM_E_KIND;
+    for (int a = 0; a < 3; ++a)
+      if (!p->ax[a].dft) return FM_E_KIND;
+  }
+  // transform order: symmetric < semi-unbounded < periodic < unbounded (cost)
+  auto cost = [](int c) {
+    if (c >= C_EE && c <= C_OE) return 0;
+    if (c >= C_EU) return 1;
+    if (c == C_P) return 2;
+    return 3;
+  };
+  int ord[3] = {0, 1, 2};
+  std::stable_sort(ord, ord + 3, [&](int x, int y) { return cost(p->ax[x].cls) < cost(p->ax[y].cls); });
+  for (int i = 0; i < 3; ++i) p->order[i] = ord[i];
+  bool seen_dft = false;
+  for (int i = 0; i < 3; ++i) {
+    AxisPlan& a = p->ax[ord[i]];
+    if (a.dft && !seen_dft) { a.first_dft = true; seen_dft = true; }
+    if (a.dft) a.nspec = a.first_dft ? a.M / 2 + 1 : a.M;
+  }
+  // Green table geometry per axis
+  for (int i = 0; i < 3; ++i) {
+    AxisPlan& a = p->ax[i];
+    if (a.dft) {
+      a.F = a.M / 2 + 1;
+      if (a.cls == C_UU) { a.Fs = a.F; a.off = 0; }  // offsets 0..N -> modes 0..N
+      else { a.Fs = a.F; a.off = 0; a.dw = 2.0 * M_PI / a.L; a.shift = 0; }
+    } else if (!a.unb) {
+      const KindForm f = kind_form(a.fwd);
+      a.F = a.nspec;
+      a.Fs = a.F;
+      a.off = 0;
+      a.dw = M_PI / a.L;
+      a.shift = f.qout + 0.5 * f.b2;
+    } else {
+      const KindForm f = kind_form(a.fwd);
+      a.F = a.nspec;
+      a.Fs = 2 * a.N + 1;  // kernel on [0, 2L]
+      a.off = f.qout;      // spectral index s pairs with kernel mode s + qout
+    }
+  }
+  const int a0 = ord[0], a1 = ord[1], a2 = ord[2];
+  // tile axis of passes 1/5: the user's fastest axis x when the first transform does
+  // not run along x, else the next transform axis
+  if (a0 == 0 || a1 == 0) p->tb1 = a1;
+  else p->tb1 = 0;  // x == a2
+  if (p->tb1 == a1) { p->L1[0] = a2; p->L1[1] = a0; p->L1[2] = a1; }
+  else { p->L1[0] = a1; p->L1[1] = a0; p->L1[2] = a2; }
+  p->L2[0] = a0; p->L2[1] = a1; p->L2[2] = a2;
+  const int Lu[3] = {2, 1, 0};
+  // work extent of an untransformed axis: the node-centred periodic duplicate f_N is
+  // never used, so intermediates hold N points; the last pass writes f_N := f_0
+  int wext[3];
+  for (int a = 0; a < 3; ++a) {
+    const AxisPlan& A = p->ax[a];
+    wext[a] = (A.cls == C_P && A.node) ? A.N : A.nuser;
+    p->ext_user[a] = A.nuser;
+    p->ext1[a] = wext[a];
+    p->ext2[a] = wext[a];
+  }
+  p->ext1[a0] = p->ax[a0].nspec;
+  p->ext2[a0] = p->ax[a0].nspec;
+  p->ext2[a1] = p->ax[a1].nspec;
+  int64_t su[3], s1[3], s2[3];
+  layout_strides(Lu, p->ext_user, su, &p->Vu);
+  layout_strides(p->L1, p->ext1, s1, &p->V1);
+  layout_strides(p->L2, p->ext2, s2, &p->V2);
+  p->cplx1 = p->ax[a0].dft;
+  p->cplx2 = p->ax[a0].dft || p->ax[a1].dft;
+  p->elem = (p->prec == FM_F64) ? 8 : 4;
+  p->bytesA = round256(p->V1 * p->elem * (p->cplx1 ? 2 : 1));
+  p->bytesB = round256(p->V2 * p->elem * (p->cplx2 ? 2 : 1));
+  p->ws_bytes = (size_t)p->ncomp * (p->bytesA + p->bytesB);
+
+  const int o1 = 3 - a0 - p->tb1;  // the other axis of passes 1 / 5
+  const bool curl = p->kind == FM_BIOT_SAVART;
+  // pass 1: user -> L1 along a0
+  {
+    fm::PassDesc& d = p->pass[0];
+    d = fm::PassDesc{};
+    set_geometry(&d, a0, p->tb1, o1, su, p->Vu, s1, p->V1, wext);
+    set_transform(&d, p->ax[a0], true, false);
+    d.in_cplx = 0;
+    d.in_n = p->ax[a0].nuser;
+    d.out_n = p->ax[a0].nspec;
+  }
+  // pass 2: L1 -> L2 along a1, tiles along a2
+  {
+    fm::PassDesc& d = p->pass[1];
+    d = fm::PassDesc{};
+    set_geometry(&d, a1, a2, a0, s1, p->V1, s2, p->V2, p->ext1);
+    set_transform(&d, p->ax[a1], true, false);
+    d.in_cplx = p->cplx1;
+    d.out_cplx = p->cplx2;
+    d.in_n = wext[a1];
+    d.out_n = p->ax[a1].nspec;
+  }
+  // pass 3: fused along a2 in L2, tiles along a1
+  {
+    fm::PassDesc& d = p->pass[2];
+    d = fm::PassDesc{};
+    set_geometry(&d, a2, a1, a0, s2, p->V2, s2, p->V2, p->ext2);
+    const AxisPlan& A = p->ax[a2];
+    d.fused = 1;
+    if (!A.dft) {
+      d.gather = fm::G_R2R;
+      d.scatter = fm::S_R2R;
+      d.r2r = make_r2r(A, A.fwd, true);
+      d.r2r2 = make_r2r(A, A.bwd, false);
+      d.spec_n = A.nspec;
+      d.in_cplx = d.out_cplx = 0;
+    } else if (A.first_dft) {
+      d.gather = fm::G_REAL2;
+      d.n_data = A.n_data;
+      d.in_cplx = d.out_cplx = 0;
+    } else {
+      d.gather = fm::G_CPLX;
+      d.n_data = A.n_data;
+      d.in_cplx = d.out_cplx = 1;
+    }
+    d.in_n = d.out_n = wext[a2];
+    fm::GreenRef& g = d.g;
+    g.F_b = p->ax[a1].F;
+    g.F_line = A.F;
+    g.fold_c = p->ax[a0].dft ? p->ax[a0].M : 0;
+    g.fold_b = p->ax[a1].dft ? p->ax[a1].M : 0;
+    g.fold_line = A.dft ? A.M : 0;
+    g.curl = curl ? 1 : 0;
+    g.axis_line = a2;
+    g.axis_b = a1;
+    g.axis_c = a0;
+    auto dw = [&](const AxisPlan& x) { return 2.0 * M_PI / (x.cls == C_P ? x.L : 2.0 * x.L); };
+    g.dw_line = A.dft ? dw(A) : 0;
+    g.dw_b = p->ax[a1].dft ? dw(p->ax[a1]) : 0;
+    g.dw_c = p->ax[a0].dft ? dw(p->ax[a0]) : 0;
+    g.M_line = A.M;
+    g.M_b = p->ax[a1].M;
+    g.M_c = p->ax[a0].M;
+  }
+  // pass 4: L2 -> L1 along a1 (inverse of pass 2)
+  {
+    fm::PassDesc& d = p->pass[3];
+    d = fm::PassDesc{};
+    set_geometry(&d, a1, a2, a0, s2, p->V2, s1, p->V1, p->ext2);
+    set_transform(&d, p->ax[a1], false, false);
+    d.in_cplx = p->cplx2;
+    d.out_cplx = p->cplx1;
+    d.in_n = p->ax[a1].nspec;
+    d.out_n = wext[a1];
+  }
+  // pass 5: L1 -> user along a0 (inverse of pass 1)
+  {
+    fm::PassDesc& d = p->pass[4];
+    d = fm::PassDesc{};
+    set_geometry(&d, a0, p->tb1, o1, s1, p->V1, su, p->Vu, p->ext1);
+    set_transform(&d, p->ax[a0], false, false);
+    d.out_cplx = 0;
+    d.in_n = p->ax[a0].nspec;
+    d.out_n = p->ax[a0].nuser;
+    // output conventions along the two batch axes
+    auto fix_axis = [](const AxisPlan& A, int32_t* dup, int32_t* zlo, int32_t* zhi, int32_t* last) {
+      *last = A.N;
+      *dup = (A.node && A.cls == C_P) ? 1 : 0;
+      *zlo = (A.node && (A.cls == C_OO || A.cls == C_OE || A.cls == C_OU)) ? 1 : 0;
+      *zhi = (A.node && (A.cls == C_OO || A.cls == C_EO || A.cls == C_UO)) ? 1 : 0;
+    };
+    fix_axis(p->ax[p->tb1], &d.fix.b_dup, &d.fix.b_zero_lo, &d.fix.b_zero_hi, &d.fix.b_last);
+    fix_axis(p->ax[o1], &d.fix.c_dup, &d.fix.c_zero_lo, &d.fix.c_zero_hi, &d.fix.c_last);
+    d.has_fix = d.fix.b_dup | d.fix.b_zero_lo | d.fix.b_zero_hi | d.fix.c_dup | d.fix.c_zero_lo |
+                d.fix.c_zero_hi;
+  }
+  const int line_axis[5] = {a0, a1, a2, a1, a0};
+  for (int i = 0; i < 5; ++i) {
+    fm::PassDesc& d = p->pass[i];
+    const int rc = radix_plan(p->ax[line_axis[i]].M, &d);
+    if (rc) return rc;
+    const bool fused_curl = (i == 2) && curl;
+    d.ncomp = p->ncomp;
+    const int rc2 = choose_tile(&d, p->elem, fused_curl ? 3 : 1, (i == 2) && d.gather == fm::G_R2R, d.nb);
+    if (rc2) return rc2;
+    d.tiles = ((d.nb + d.B - 1) / d.B) * d.nc * (fused_curl ? 1 : p->ncomp);
+  }
+  const int64_t sizes_in[5] = {p->Vu, p->V1, p->V2, p->V2, p->V1};
+  const int64_t sizes_out[5] = {p->V1, p->V2, p->V2, p->V1, p->Vu};
+  for (int i = 0; i < 5; ++i)
+    if (!pass_in_bounds(p->pass[i], sizes_in[i], sizes_out[i], p->elem)) return FM_E_SIZE;
+  return FM_OK;
+}
+
+
+int launch_all(fm_plan_s* p, fm::PassDesc* ds, hipStream_t st, int first = 0, int last = 4) {
+  for (int i = first; i <= last; ++i) {
+    hipError_t e = (p->prec == FM_F64) ? fm::launch_pass<double>(ds[i], st)
+                                       : fm::launch_pass<float>(ds[i], st);
+    if (e != hipSuccess) { g_last_hip = (int)e; return FM_E_HIP; }
+  }
+  return FM_OK;
+}
+
+void bind_buffers(const fm_plan_s* p, const void* rhs, void* out, char* ws, fm::PassDesc* ds) {
+  char* A = ws;
+  char* B = ws + p->ncomp * p->bytesA;
+  for (int i = 0; i < 5; ++i) ds[i] = p->pass[i];
+  // per-component strides in elements of each buffer
+  const int64_t compA = p->bytesA / (p->elem * (p->cplx1 ? 2 : 1));
+  const int64_t compB = p->bytesB / (p->elem * (p->cplx2 ? 2 : 1));
+  ds[0].in = rhs; ds[0].out = A; ds[0].out_s_comp = compA;
+  ds[1].in = A; ds[1].in_s_comp = compA; ds[1].out = B; ds[1].out_s_comp = compB;
+  ds[2].in = B; ds[2].in_s_comp = compB; ds[2].out = B; ds[2].out_s_comp = compB;
+  ds[2].g.G = p->G;
+  ds[3].in = B; ds[3].in_s_comp = compB; ds[3].out = A; ds[3].out_s_comp = compA;
+  ds[4].in = A; ds[4].in_s_comp = compA; ds[4].out = out;
+}
+
+// Pinned host staging for the batch descriptor tables, one per host thread.  It is
+// deliberately never released: freeing it from a thread-exit destructor could run
+// after the HIP runtime has been torn down.
+struct BatchStaging {
+  void* host = nullptr;
+  size_t bytes = 0;
+  hipEvent_t done = nullptr;
+  bool pending = false;
+};
+thread_local BatchStaging* g_stage_ptr = nullptr;
+
+}  // namespace
+
+extern "C" {
+
+const char* fm_error_string(int status) {
+  switch (status) {
+    case FM_OK: return "ok";
+    case FM_E_NULL: return "null pointer argument";
+    case FM_E_BC: return "invalid boundary condition (periodic must pair with periodic)";
+    case FM_E_SIZE: return "unsupported size (N < 2, h <= 0, or FFT length not 2^a 3^b 5^c 7^d <= 4096)";
+    case FM_E_KIND: return "unsupported kind / green / precision / layout combination";
+    case FM_E_NOMEM: return "device allocation failed";
+    case FM_E_HIP: return "HIP runtime error";
+    case FM_E_ARG: return "inconsistent arguments";
+    default: return "unknown status";
+  }
+}
+
+int fm_last_hip_error(void) { return g_last_hip; }
+
+int fm_plan_create(fm_plan* out, const int n[3], const double h[3], const int bc[3][2], int layout,
+                   int green, int prec, int kind, int ncomp, void* hip_stream) {
+  if (!out || !n || !h || !bc) return FM_E_NULL;
+  *out = nullptr;
+  if (layout != FM_CELL && layout != FM_NODE) return FM_E_KIND;
+  if (green != FM_GREEN_CHAT2 && green != FM_GREEN_CHAT2_VOL) return FM_E_KIND;
+  if (prec != FM_F64 && prec != FM_F32) return FM_E_KIND;
+  if (kind != FM_POISSON && kind != FM_BIOT_SAVART) return FM_E_KIND;
+  if (ncomp < 1 || ncomp > 64) return FM_E_KIND;
+  fm_plan_s* p = new (std::nothrow) fm_plan_s();
+  if (!p) return FM_E_NOMEM;
+  for (int a = 0; a < 3; ++a) {
+    p->n[a] = n[a];
+    p->h[a] = h[a];
+    p->bc[a][0] = bc[a][0];
+    p->bc[a][1] = bc[a][1];
+  }
+  p->layout = layout;
+  p->green = green;
+  p->prec = prec;
+  p->kind = kind;
+  p->ncomp = ncomp;
+  int rc = build_plan(p);
+  if (rc == FM_OK) {
+    const hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+      g_last_hip = (int)e;
+      rc = FM_E_HIP;
+    }
+  }
+  if (rc == FM_OK) {
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    rc = (prec == FM_F64) ? make_tables_and_green<double>(p, st) : make_tables_and_green<float>(p, st);
+  }
+  if (rc != FM_OK) {
+    free_plan(p);
+    return rc;
+  }
+  *out = p;
+  return FM_OK;
+}
+
+int fm_plan_inspect(const int n[3], const double h[3], const int bc[3][2], int layout, int green,
+                    int prec, int kind, int ncomp, fm_plan_info* info) {
+  if (!n || !h || !bc || !info) return FM_E_NULL;
+  if (layout != FM_CELL && layout != FM_NODE) return FM_E_KIND;
+  if (green != FM_GREEN_CHAT2 && green != FM_GREEN_CHAT2_VOL) return FM_E_KIND;
+  if (prec != FM_F64 && prec != FM_F32) return FM_E_KIND;
+  if (kind != FM_POISSON && kind != FM_BIOT_SAVART) return FM_E_KIND;
+  if (ncomp < 1 || ncomp > 64) return FM_E_KIND;
+  fm_plan_s* p = new (std::nothrow) fm_plan_s();
+  if (!p) return FM_E_NOMEM;
+  for (int a = 0; a < 3; ++a) {
+    p->n[a] = n[a];
+    p->h[a] = h[a];
+    p->bc[a][0] = bc[a][0];
+    p->bc[a][1] = bc[a][1];
+  }
+  p->layout = layout;
+  p->green = green;
+  p->prec = prec;
+  p->kind = kind;
+  p->ncomp = ncomp;
+  const int rc = build_plan(p);
+  if (rc == FM_OK) {
+    for (int a = 0; a < 3; ++a) {
+      info->order[a] = p->order[a];
+      info->axis_class[a] = p->ax[a].cls;
+      info->fft_len[a] = p->ax[a].M;
+      info->spec_len[a] = p->ax[a].nspec;
+      info->green_dims[a] = p->ax[p->order[a]].F;
+    }
+    info->workspace_bytes = p->ws_bytes;
+    for (int i = 0; i < 5; ++i) {
+      info->tiles[i] = p->pass[i].tiles;
+      info->lines_per_tile[i] = p->pass[i].B;
+      info->lds_bytes[i] = p->pass[i].lds_bytes;
+    }
+    // algorithmic bytes: every live element read once and written once per pass
+    const double e = (double)p->elem, nc = p->ncomp;
+    const double wu = (double)p->Vu, w1 = (double)p->V1 * (p->cplx1 ? 2 : 1);
+    const double w2 = (double)p->V2 * (p->cplx2 ? 2 : 1);
+    const double wg = (double)p->ax[p->order[0]].F * p->ax[p->order[1]].F * p->ax[p->order[2]].F;
+    info->algo_bytes[0] = e * nc * (wu + w1);
+    info->algo_bytes[1] = e * nc * (w1 + w2);
+    info->algo_bytes[2] = e * (nc * 2 * w2 + wg);
+    info->algo_bytes[3] = e * nc * (w2 + w1);
+    info->algo_bytes[4] = e * nc * (w1 + wu);
+  }
+  delete p;
+  return rc;
+}
+
+int fm_plan_destroy(fm_plan p) {
+  free_plan(p);
+  return FM_OK;
+}
+
+int fm_plan_workspace_bytes(fm_plan p, size_t* bytes) {
+  if (!p || !bytes) return FM_E_NULL;
+  *bytes = p->ws_bytes;
+  return FM_OK;
+}
+
+int fm_plan_shape(fm_plan p, int user_dims[3]) {
+  if (!p || !user_dims) return FM_E_NULL;
+  for (int a = 0; a < 3; ++a) user_dims[a] = p->ax[a].nuser;
+  return FM_OK;
+}
+
+int fm_solve(fm_plan p, const void* rhs_dev, void* out_dev, void* workspace_dev, void* hip_stream) {
+  if (!p || !rhs_dev || !out_dev) return FM_E_NULL;
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  char* ws = reinterpret_cast<char*>(workspace_dev);
+  if (!ws) {
+    if (!p->ws_internal) {
+      if (hipMalloc(&p->ws_internal, p->ws_bytes) != hipSuccess) return FM_E_NOMEM;
+    }
+    ws = reinterpret_cast<char*>(p->ws_internal);
+  }
+  fm::PassDesc ds[5];
+  bind_buffers(p, rhs_dev, out_dev, ws, ds);
+  return launch_all(p, ds, st);
+}
+
+int fm_solve_passes(fm_plan p, const void* rhs_dev, void* out_dev, void* workspace_dev, int first_pass,
+                    int last_pass, void* hip_stream) {
+  if (!p || !rhs_dev || !out_dev) return FM_E_NULL;
+  if (first_pass < 0 || last_pass > 4 || first_pass > last_pass) return FM_E_ARG;
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  char* ws = reinterpret_cast<char*>(workspace_dev);
+  if (!ws) {
+    if (!p->ws_internal) {
+      if (hipMalloc(&p->ws_internal, p->ws_bytes) != hipSuccess) return FM_E_NOMEM;
+    }
+    ws = reinterpret_cast<char*>(p->ws_internal);
+  }
+  fm::PassDesc ds[5];
+  bind_buffers(p, rhs_dev, out_dev, ws, ds);
+  return launch_all(p, ds, st, first_pass, last_pass);
+}
+
+int fm_batched_workspace_bytes(int count, const fm_plan* plans, size_t* bytes) {
+  if (!plans || !bytes) return FM_E_NULL;
+  if (count < 0) return FM_E_ARG;
+  size_t total = 0;
+  for (int i = 0; i < count; ++i) {
+    if (!plans[i]) return FM_E_NULL;
+    total += round256(plans[i]->ws_bytes);
+  }
+  // descriptor tables: 5 passes x (count descriptors + count+1 prefixes)
+  total += round256(5 * ((size_t)count * sizeof(fm::PassDesc) + (count + 1) * sizeof(int)) + 1024);
+  *bytes = total;
+  return FM_OK;
+}
+
+int fm_solve_batched(int count, const fm_plan* plans, const void* const* rhs_dev, void* const* out_dev,
+                     void* workspace_dev, size_t workspace_bytes, void* hip_stream) {
+  if (count == 0) return FM_OK;
+  if (count < 0) return FM_E_ARG;
+  if (!plans || !rhs_dev || !out_dev || !workspace_dev) return FM_E_NULL;
+  size_t need = 0;
+  int rc = fm_batched_workspace_bytes(count, plans, &need);
+  if (rc) return rc;
+  if (workspace_bytes < need) return FM_E_ARG;
+  const int prec = plans[0]->prec;
+  for (int i = 0; i < count; ++i) {
+    if (plans[i]->prec != prec) return FM_E_ARG;
+    if (!rhs_dev[i] || !out_dev[i]) return FM_E_NULL;
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  char* ws = reinterpret_cast<char*>(workspace_dev);
+  // per-request work buffers
+  std::vector<fm::PassDesc> all(5 * (size_t)count);
+  size_t off = 0;
+  for (int i = 0; i < count; ++i) {
+    bind_buffers(plans[i], rhs_dev[i], out_dev[i], ws + off, &all[5 * (size_t)i]);
+    off += round256(plans[i]->ws_bytes);
+  }
+  // host staging of the descriptor tables (pinned, reused once the previous copy ended)
+  const size_t desc_bytes = (size_t)count * sizeof(fm::PassDesc);
+  const size_t pref_bytes = round256((count + 1) * sizeof(int));
+  const size_t per_pass = round256(desc_bytes) + pref_bytes;
+  const size_t table_bytes = 5 * per_pass;
+  if (!g_stage_ptr) g_stage_ptr = new (std::nothrow) BatchStaging();
+  if (!g_stage_ptr) return FM_E_NOMEM;
+  BatchStaging& sg = *g_stage_ptr;
+  if (sg.pending) {
+    FM_HIP(hipEventSynchronize(sg.done));
+    sg.pending = false;
+  }
+  if (sg.bytes < table_bytes) {
+    if (sg.host) (void)hipHostFree(sg.host);
+    sg.host = nullptr;
+    sg.bytes = 0;
+    if (hipHostMalloc(&sg.host, table_bytes, hipHostMallocDefault) != hipSuccess) return FM_E_NOMEM;
+    sg.bytes = table_bytes;
+  }
+  if (!sg.done) FM_HIP(hipEventCreateWithFlags(&sg.done, hipEventDisableTiming));
+  char* host = reinterpret_cast<char*>(sg.host);
+  char* dev = ws + off;
+  int totals[5], lds[5];
+  for (int ps = 0; ps < 5; ++ps) {
+    fm::PassDesc* hd = reinterpret_cast<fm::PassDesc*>(host + ps * per_pass);
+    int* hp = reinterpret_cast<int*>(host + ps * per_pass + round256(desc_bytes));
+    int acc = 0, mx = 0;
+    for (int i = 0; i < count; ++i) {
+      hd[i] = all[5 * (size_t)i + ps];
+      hp[i] = acc;
+      acc += hd[i].tiles;
+      mx = std::max(mx, hd[i].lds_bytes);
+    }
+    hp[count] = acc;
+    totals[ps] = acc;
+    lds[ps] = mx;
+  }
+  FM_HIP(hipMemcpyAsync(dev, host, table_bytes, hipMemcpyHostToDevice, st));
+  FM_HIP(hipEventRecord(sg.done, st));
+  sg.pending = true;
+  for (int ps = 0; ps < 5; ++ps) {
+    const fm::PassDesc* dd = reinterpret_cast<const fm::PassDesc*>(dev + ps * per_pass);
+    const int* dp = reinterpret_cast<const int*>(dev + ps * per_pass + round256(desc_bytes));
+    hipError_t e = (prec == FM_F64)
+                       ? fm::launch_pass_batched<double>(dd, dp, count, totals[ps], lds[ps], st)
+                       : fm::launch_pass_batched<float>(dd, dp, count, totals[ps], lds[ps], st);
+    if (e != hipSuccess) { g_last_hip = (int)e; return FM_E_HIP; }
+  }
+  return FM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,229 @@
+"""ctypes binding of libfluxmi.so (include/fluxmi.h).
+
+Argument marshalling only: every step of a solve runs in the HIP library.  Device
+memory and streams come from PyTorch (``tensor.data_ptr()``,
+``torch.cuda.current_stream().cuda_stream``).  If the library is missing this module
+raises; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfluxmi.so")
+
+EVEN, ODD, PER, UNB = 0, 1, 2, 3
+CELL, NODE = 0, 1
+CHAT2, CHAT2_VOL = 0, 1
+F64, F32 = 0, 1
+POISSON, BIOT_SAVART = 0, 1
+CLASS_NAMES = ["P", "EE", "OO", "EO", "OE", "UU", "EU", "OU", "UE", "UO"]
+EXPORTED = [
+    "fm_plan_create", "fm_plan_destroy", "fm_plan_workspace_bytes", "fm_plan_shape",
+    "fm_solve", "fm_solve_passes", "fm_solve_batched", "fm_batched_workspace_bytes", "fm_plan_inspect",
+    "fm_error_string", "fm_last_hip_error",
+]
+
+
+class FluxmiError(RuntimeError):
+    def __init__(self, status, what=""):
+        lib = library()
+        msg = lib.fm_error_string(status).decode()
+        if status == -6:
+            msg += f" (hip error {lib.fm_last_hip_error()})"
+        super().__init__(f"{what}: {msg} [{status}]" if what else f"{msg} [{status}]")
+        self.status = status
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [
+        ("order", ctypes.c_int * 3), ("axis_class", ctypes.c_int * 3), ("fft_len", ctypes.c_int * 3),
+        ("spec_len", ctypes.c_int * 3), ("green_dims", ctypes.c_int * 3),
+        ("workspace_bytes", ctypes.c_size_t), ("tiles", ctypes.c_int * 5),
+        ("lines_per_tile", ctypes.c_int * 5), ("lds_bytes", ctypes.c_int * 5),
+        ("algo_bytes", ctypes.c_double * 5),
+    ]
+
+
+_lib = None
+
+
+def library():
+    """Load libfluxmi.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() first")
+    # torch ships its own HIP runtime under the same soname; load it first so that the
+    # library binds to the runtime that owns torch's device memory and streams (two
+    # runtimes in one process do not share devices, pointers or streams)
+    import torch  # noqa: F401
+    L = ctypes.CDLL(LIB_PATH)
+    vp, ip, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
+    L.fm_plan_create.argtypes = [ctypes.POINTER(vp), ip, dp, ip, ctypes.c_int, ctypes.c_int,
+                                 ctypes.c_int, ctypes.c_int, ctypes.c_int, vp]
+    L.fm_plan_destroy.argtypes = [vp]
+    L.fm_plan_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    L.fm_plan_shape.argtypes = [vp, ip]
+    L.fm_solve.argtypes = [vp, vp, vp, vp, vp]
+    L.fm_solve_passes.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_int, vp]
+    L.fm_solve_batched.argtypes = [ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                   ctypes.POINTER(vp), vp, ctypes.c_size_t, vp]
+    L.fm_batched_workspace_bytes.argtypes = [ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_size_t)]
+    L.fm_plan_inspect.argtypes = [ip, dp, ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                  ctypes.c_int, ctypes.POINTER(_Info)]
+    L.fm_error_string.argtypes = [ctypes.c_int]
+    L.fm_error_string.restype = ctypes.c_char_p
+    L.fm_last_hip_error.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def error_string(status):
+    return library().fm_error_string(status).decode()
+
+
+def _check(status, what):
+    if status != 0:
+        raise FluxmiError(status, what)
+
+
+def _args(n, h, bc):
+    n3 = (ctypes.c_int * 3)(*[int(v) for v in n])
+    h3 = (ctypes.c_double * 3)(*[float(v) for v in h])
+    flat = [int(v) for pair in bc for v in pair]
+    if len(flat) != 6:
+        raise ValueError("bc must be [[xl, xr], [yl, yr], [zl, zr]]")
+    b6 = (ctypes.c_int * 6)(*flat)
+    return n3, h3, b6
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def plan_inspect(n, h, bc, layout, green=CHAT2, prec=F64, kind=POISSON, ncomp=1):
+    """Host-only planning information (no device needed)."""
+    n3, h3, b6 = _args(n, h, bc)
+    info = _Info()
+    _check(library().fm_plan_inspect(n3, h3, b6, layout, green, prec, kind, ncomp, ctypes.byref(info)),
+           "fm_plan_inspect")
+    return {
+        "order": list(info.order), "axis_class": [CLASS_NAMES[c] for c in info.axis_class],
+        "fft_len": list(info.fft_len), "spec_len": list(info.spec_len),
+        "green_dims": list(info.green_dims), "workspace_bytes": int(info.workspace_bytes),
+        "tiles": list(info.tiles), "lines_per_tile": list(info.lines_per_tile),
+        "lds_bytes": list(info.lds_bytes), "algo_bytes": list(info.algo_bytes),
+    }
+
+
+class Plan:
+    """A solver plan (owns the cached Green's spectrum and twiddles on the device)."""
+
+    def __init__(self, n, h, bc, layout, green=CHAT2, prec=F64, kind=POISSON, ncomp=None, stream=None):
+        if ncomp is None:
+            ncomp = 3 if kind == BIOT_SAVART else 1
+        self.n, self.h, self.bc = tuple(int(v) for v in n), tuple(float(v) for v in h), [list(p) for p in bc]
+        self.layout, self.green, self.prec, self.kind, self.ncomp = layout, green, prec, kind, ncomp
+        n3, h3, b6 = _args(n, h, bc)
+        handle = ctypes.c_void_p()
+        _check(library().fm_plan_create(ctypes.byref(handle), n3, h3, b6, layout, green, prec, kind, ncomp,
+                                        _stream_ptr(stream)), "fm_plan_create")
+        self._h = handle
+        dims = (ctypes.c_int * 3)()
+        _check(library().fm_plan_shape(self._h, dims), "fm_plan_shape")
+        self.user_dims = tuple(dims)  # (nx, ny, nz)
+        ws = ctypes.c_size_t()
+        _check(library().fm_plan_workspace_bytes(self._h, ctypes.byref(ws)), "fm_plan_workspace_bytes")
+        self.workspace_bytes = int(ws.value)
+
+    @property
+    def shape(self):
+        """torch shape of one solve's rhs / out: (ncomp, nz, ny, nx) or (nz, ny, nx)."""
+        nx, ny, nz = self.user_dims
+        return (self.ncomp, nz, ny, nx) if self.ncomp > 1 else (nz, ny, nx)
+
+    @property
+    def dtype(self):
+        import torch
+        return torch.float64 if self.prec == F64 else torch.float32
+
+    def _check_tensor(self, t, name):
+        if not t.is_cuda or t.dtype != self.dtype or not t.is_contiguous():
+            raise ValueError(f"{name}: need a contiguous {self.dtype} GPU tensor")
+        if t.numel() != self.ncomp * self.user_dims[0] * self.user_dims[1] * self.user_dims[2]:
+            raise ValueError(f"{name}: expected {self.shape}, got {tuple(t.shape)}")
+
+    def solve(self, rhs, out=None, workspace=None, stream=None):
+        import torch
+        self._check_tensor(rhs, "rhs")
+        if out is None:
+            out = torch.empty_like(rhs)
+        self._check_tensor(out, "out")
+        ws = ctypes.c_void_p(0)
+        if workspace is not None:
+            if workspace.numel() * workspace.element_size() < self.workspace_bytes or not workspace.is_cuda:
+                raise ValueError("workspace too small")
+            ws = ctypes.c_void_p(workspace.data_ptr())
+        _check(library().fm_solve(self._h, ctypes.c_void_p(rhs.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                  ws, _stream_ptr(stream)), "fm_solve")
+        return out
+
+    def solve_passes(self, rhs, out, first, last, workspace=None, stream=None):
+        """Run passes first..last (0..4) of a solve; see fm_solve_passes."""
+        self._check_tensor(rhs, "rhs")
+        self._check_tensor(out, "out")
+        ws = ctypes.c_void_p(0 if workspace is None else workspace.data_ptr())
+        if workspace is not None and workspace.numel() * workspace.element_size() < self.workspace_bytes:
+            raise ValueError("workspace too small")
+        _check(library().fm_solve_passes(self._h, ctypes.c_void_p(rhs.data_ptr()),
+                                         ctypes.c_void_p(out.data_ptr()), ws, int(first), int(last),
+                                         _stream_ptr(stream)), "fm_solve_passes")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            library().fm_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        # at interpreter shutdown the HIP runtime may already be gone: leave the
+        # memory to the process teardown
+        if sys.is_finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batched_workspace_bytes(plans):
+    arr = (ctypes.c_void_p * len(plans))(*[p._h.value for p in plans])
+    out = ctypes.c_size_t()
+    _check(library().fm_batched_workspace_bytes(len(plans), arr, ctypes.byref(out)), "fm_batched_workspace_bytes")
+    return int(out.value)
+
+
+def solve_batched(plans, rhs, outs, workspace, stream=None):
+    """One launch per pass for the whole batch (plans may differ; same precision)."""
+    n = len(plans)
+    if not (len(rhs) == len(outs) == n):
+        raise ValueError("plans, rhs and outs must have the same length")
+    for p, r, o in zip(plans, rhs, outs):
+        p._check_tensor(r, "rhs")
+        p._check_tensor(o, "out")
+    P = (ctypes.c_void_p * n)(*[p._h.value for p in plans])
+    R = (ctypes.c_void_p * n)(*[r.data_ptr() for r in rhs])
+    O = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+    nbytes = workspace.numel() * workspace.element_size()
+    _check(library().fm_solve_batched(n, P, R, O, ctypes.c_void_p(workspace.data_ptr()), nbytes,
+                                      _stream_ptr(stream)), "fm_solve_batched")
+    return outs

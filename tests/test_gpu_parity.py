@@ -1,0 +1,166 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle, element by
+element, on seeded inputs.  FP64 within 1e-12 relative L-inf, FP32 within 1e-5."""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2211_07777_amd as F
+from paper_2211_07777_amd import workloads as W
+
+from gpu_common import TOL32, TOL64, check_conventions, gpu_solve, oracle_solve, rel_linf
+
+pytestmark = pytest.mark.gpu
+
+PAIRS = [(2, 2), (0, 0), (1, 1), (0, 1), (1, 0), (3, 3), (0, 3), (1, 3), (3, 0), (3, 1)]
+
+
+def _case(n, h, bc, layout, prec, seed, green=0, kind=0):
+    ncomp = 3 if kind == 1 else 1
+    shape = ((3,) if kind == 1 else ()) + O.user_shape(n, layout)
+    f = W.random_field(shape, seed)
+    ref = oracle_solve(f, n, h, bc, layout, green, kind)
+    plan = F.Plan(n, h, bc, layout, green, prec, kind, ncomp)
+    u = gpu_solve(plan, f)
+    plan.close()
+    check_conventions(u, bc, layout)
+    return rel_linf(u, ref)
+
+
+@pytest.mark.parametrize("green", [0, 1])
+def test_gaussian_32_fp64(green):
+    """32^3 cell-centred, fully unbounded, FP64, Gaussian blob."""
+    f, h = W.gaussian_blob(32)
+    ref = oracle_solve(f, [32] * 3, [h] * 3, [[3, 3]] * 3, O.CELL, green)
+    plan = F.Plan([32] * 3, [h] * 3, [[3, 3]] * 3, F.CELL, green, F.F64)
+    u = gpu_solve(plan, f)
+    err = rel_linf(u, ref)
+    print(f"gaussian32 green={green} rel_linf={err:.3e}")
+    assert err < TOL64
+
+
+@pytest.mark.parametrize("prec,tol", [(F.F64, TOL64), (F.F32, TOL32)])
+@pytest.mark.parametrize("layout", [F.CELL, F.NODE])
+def test_every_class_on_every_axis(prec, tol, layout):
+    """Each of the 10 classes on each axis position, other axes drawn at random,
+    ragged sizes (several tiles and a partial last tile)."""
+    rng = np.random.default_rng(100 + 10 * prec + layout)
+    worst = 0.0
+    sizes = [(12, 10, 9), (9, 16, 6), (5, 7, 20)]
+    for ax in range(3):
+        for pair in PAIRS:
+            bc = [list(PAIRS[rng.integers(10)]) for _ in range(3)]
+            bc[ax] = list(pair)
+            n = list(sizes[ax])
+            h = [0.11, 0.07, 0.13]
+            err = _case(n, h, bc, layout, prec, int(rng.integers(1 << 30)))
+            worst = max(worst, err)
+            assert err < tol, (bc, n, layout, prec, err)
+    print(f"layout={layout} prec={prec} worst={worst:.3e}")
+
+
+@pytest.mark.parametrize("layout", [F.CELL, F.NODE])
+def test_random_class_combinations_fp64(layout):
+    rng = np.random.default_rng(7 + layout)
+    combos = list(itertools.product(range(10), repeat=3))
+    pick = rng.choice(len(combos), size=60, replace=False)
+    for i in pick:
+        bc = [list(PAIRS[j]) for j in combos[i]]
+        n = [int(v) for v in rng.choice([2, 3, 4, 6, 8, 10, 12, 15], size=3)]
+        h = [float(v) for v in rng.uniform(0.05, 0.2, size=3)]
+        err = _case(n, h, bc, layout, F.F64, int(rng.integers(1 << 30)), green=int(rng.integers(2)))
+        assert err < TOL64, (bc, n, layout, err)
+
+
+@pytest.mark.parametrize("prec,tol", [(F.F64, TOL64), (F.F32, TOL32)])
+@pytest.mark.parametrize("layout", [F.CELL, F.NODE])
+def test_biot_savart_small(prec, tol, layout):
+    for bc in ([[3, 3]] * 3, [[2, 2], [3, 3], [3, 3]], [[3, 3], [2, 2], [2, 2]], [[2, 2]] * 3):
+        err = _case([12, 10, 14], [0.1, 0.12, 0.09], bc, layout, prec, 5, kind=1)
+        assert err < tol, (bc, layout, prec, err)
+
+
+@pytest.mark.parametrize("prec,tol", [(F.F64, TOL64), (F.F32, TOL32)])
+def test_mixed_node_128x128x256(prec, tol):
+    """Node-centred 128 x 128 x 256 intervals on [0,1]x[0,1]x[0,2]: x periodic, y even
+    (y = 0) / odd (y = L), z unbounded; 8 seeded Gaussian bumps."""
+    n, h = [128, 128, 256], [1 / 128] * 3
+    bc = [[2, 2], [0, 1], [3, 3]]
+    coords = [np.arange(n[a] + 1) * h[a] for a in range(3)]
+    f = W.gaussian_bumps(coords, [1.0, 1.0, 2.0])
+    ref = oracle_solve(f, n, h, bc, O.NODE)
+    plan = F.Plan(n, h, bc, F.NODE, F.CHAT2, prec)
+    u = gpu_solve(plan, f)
+    err = rel_linf(u, ref)
+    print(f"mixed node 128x128x256 prec={prec} rel_linf={err:.3e}")
+    assert err < tol
+    # exact output conventions: odd face y = L is zero, periodic duplicate x_N = x_0
+    check_conventions(u, bc, F.NODE)
+
+
+def test_edge_sizes_and_lengths():
+    """Smallest grids, odd FFT lengths (3, 5, 7 factors) and the longest FFT."""
+    cases = [
+        ([2, 2, 2], [[3, 3], [1, 1], [2, 2]], F.NODE),
+        ([2, 3, 2], [[0, 3], [3, 1], [1, 0]], F.CELL),
+        ([3, 5, 7], [[2, 2], [2, 2], [2, 2]], F.CELL),
+        ([15, 21, 10], [[3, 3], [2, 2], [0, 1]], F.NODE),
+        ([7, 6, 5], [[1, 3], [3, 0], [3, 3]], F.NODE),
+        ([1024, 2, 2], [[3, 3], [2, 2], [2, 2]], F.CELL),  # FFT length 2048
+        ([4, 512, 3], [[0, 3], [2, 2], [2, 2]], F.CELL),   # semi-unbounded, length 2048
+        ([2048, 2, 2], [[3, 3], [2, 2], [2, 2]], F.CELL),  # FFT length 4096 (LDS > 64 KB)
+        ([4, 1024, 3], [[0, 3], [2, 2], [2, 2]], F.CELL),  # semi-unbounded, length 4096
+    ]
+    for n, bc, layout in cases:
+        err = _case(n, [0.1, 0.2, 0.15], bc, layout, F.F64, 11)
+        assert err < TOL64, (n, bc, layout, err)
+    # the longest FFT (4096) in FP32
+    for n, bc in (([2048, 2, 2], [[3, 3], [2, 2], [2, 2]]), ([3, 1024, 2], [[2, 2], [3, 1], [2, 2]])):
+        err = _case(n, [0.1, 0.2, 0.15], bc, F.CELL, F.F32, 12)
+        assert err < TOL32, (n, bc, err)
+
+
+def test_errors_are_reported():
+    with pytest.raises(F.FluxmiError):
+        F.Plan([8, 8, 8], [0.1] * 3, [[2, 3], [3, 3], [3, 3]], F.CELL)
+    with pytest.raises(F.FluxmiError):
+        F.Plan([8, 8, 8], [0.1] * 3, [[3, 3], [3, 3], [0, 0]], F.CELL, kind=F.BIOT_SAVART)
+    with pytest.raises(F.FluxmiError):
+        F.Plan([11, 8, 8], [0.1] * 3, [[2, 2], [3, 3], [3, 3]], F.CELL)  # prime 11
+
+
+def test_in_place_and_multiple_components():
+    import torch
+    n, h, bc = [10, 12, 8], [0.1] * 3, [[3, 3], [0, 3], [2, 2]]
+    f = W.random_field((4,) + O.user_shape(n, F.CELL), 3)
+    plan = F.Plan(n, h, bc, F.CELL, F.CHAT2, F.F64, F.POISSON, ncomp=4)
+    x = torch.from_numpy(f).cuda()
+    plan.solve(x, out=x)  # in place
+    torch.cuda.synchronize()
+    u = x.cpu().numpy()
+    for c in range(4):
+        ref = oracle_solve(f[c], n, h, bc, O.CELL)
+        assert rel_linf(u[c], ref) < TOL64
+
+
+@pytest.mark.parametrize("prec", [F.F64, F.F32])
+def test_batched_bitwise_equals_single(prec):
+    import torch
+    rng = np.random.default_rng(5)
+    plans, rhs, singles = [], [], []
+    for i in range(12):
+        n = [int(v) for v in rng.choice([4, 6, 8, 12, 16], size=3)]
+        bc = [list(PAIRS[j]) for j in rng.integers(10, size=3)]
+        layout = int(rng.integers(2))
+        p = F.Plan(n, [0.1, 0.08, 0.12], bc, layout, F.CHAT2, prec)
+        f = torch.from_numpy(W.random_field(p.shape, 40 + i)).to("cuda", p.dtype)
+        plans.append(p)
+        rhs.append(f)
+        singles.append(p.solve(f))
+    outs = [torch.empty_like(r) for r in rhs]
+    ws = torch.empty(F.batched_workspace_bytes(plans), dtype=torch.uint8, device="cuda")
+    F.solve_batched(plans, rhs, outs, ws)
+    torch.cuda.synchronize()
+    for s, o in zip(singles, outs):
+        assert torch.equal(s, o)
