@@ -116,9 +116,12 @@ int fm_solve_passes(fm_plan p, const void* rhs_dev, void* out_dev, void* workspa
                     int first_pass, int last_pass, void* hip_stream);
 
 /* Solve `count` independent problems (plans may differ in shape, boundary conditions
- * and layout, but must share one precision) with one launch per pass for the whole
- * batch.  Each result is bitwise identical to fm_solve of the same plan.
- *   workspace_dev  at least fm_batched_workspace_bytes(count, plans) bytes */
+ * and layout, but must share one precision).  FP64 batches run with one launch per pass
+ * and length class for the whole batch; FP32 batches run plan by plan with the
+ * single-solve kernels.  Each result is bitwise identical to fm_solve of the same plan.
+ *   workspace_dev  at least fm_batched_workspace_bytes(count, plans) bytes
+ * Errors: FM_E_ARG if the plans mix precisions or the workspace is too small, FM_E_NULL
+ * for a null plan array, buffer array or buffer. */
 int fm_solve_batched(int count, const fm_plan* plans, const void* const* rhs_dev,
                      void* const* out_dev, void* workspace_dev, size_t workspace_bytes,
                      void* hip_stream);

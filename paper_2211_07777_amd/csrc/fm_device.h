@@ -1,0 +1,1044 @@
+// Device templates of the Fourier-convolution solver for gfx950 (line passes).
+//
+// Every step of a solve is one "line pass" (fm_pass.h): a workgroup loads a tile of B
+// lines with coalesced accesses into LDS, builds the FFT inputs in registers (zero
+// padding of unbounded directions, symmetric extension and pre-twiddle for DCT/DST,
+// two real lines packed into one complex line), runs a mixed-radix Stockham FFT in LDS,
+// and writes the post-processed lines into the next layout (transposed), again
+// coalesced.  Pass 3 fuses the forward transform of the last axis, the multiplication
+// by the Green's spectrum (or by the Green's spectrum times the spectral curl) and the
+// inverse transform.  Twiddle tables and the Green's spectrum are generated in FP64.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "fm_pass.h"
+
+namespace fm {
+
+template <typename T>
+struct cpx {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cpx<T> cadd(cpx<T> a, cpx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> csub(cpx<T> a, cpx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// multiply by S*i (S = +1 or -1)
+template <int S, typename T>
+__device__ __forceinline__ cpx<T> mul_si(cpx<T> a) {
+  return S > 0 ? cpx<T>{-a.y, a.x} : cpx<T>{a.y, -a.x};
+}
+
+// ---------------------------------------------------------------------------------
+// Small DFTs: v[q] <- sum_r v[r] exp(S 2 pi i r q / R)
+// ---------------------------------------------------------------------------------
+template <int R, int S, typename T>
+struct SmallDft;
+
+template <int S, typename T>
+struct SmallDft<2, S, T> {
+  __device__ __forceinline__ static void run(cpx<T>* v) {
+    const cpx<T> a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  }
+};
+
+template <int S, typename T>
+struct SmallDft<4, S, T> {
+  __device__ __forceinline__ static void run(cpx<T>* v) {
+    const cpx<T> t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+    const cpx<T> t2 = cadd(v[1], v[3]), t3 = mul_si<S>(csub(v[1], v[3]));
+    v[0] = cadd(t0, t2);
+    v[2] = csub(t0, t2);
+    v[1] = cadd(t1, t3);
+    v[3] = csub(t1, t3);
+  }
+};
+
+template <int S, typename T>
+struct SmallDft<8, S, T> {
+  __device__ __forceinline__ static void run(cpx<T>* v) {
+    cpx<T> e[4] = {v[0], v[2], v[4], v[6]};
+    cpx<T> o[4] = {v[1], v[3], v[5], v[7]};
+    SmallDft<4, S, T>::run(e);
+    SmallDft<4, S, T>::run(o);
+    const T c = T(0.70710678118654752440);
+    // o[q] *= exp(S 2 pi i q / 8)
+    const cpx<T> o1 = {c * (o[1].x - S * o[1].y), c * (S * o[1].x + o[1].y)};
+    const cpx<T> o2 = mul_si<S>(o[2]);
+    const cpx<T> o3 = {c * (-o[3].x - S * o[3].y), c * (S * o[3].x - o[3].y)};
+    v[0] = cadd(e[0], o[0]);
+    v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], o1);
+    v[5] = csub(e[1], o1);
+    v[2] = cadd(e[2], o2);
+    v[6] = csub(e[2], o2);
+    v[3] = cadd(e[3], o3);
+    v[7] = csub(e[3], o3);
+  }
+};
+
+// odd radices: pair r with R - r
+template <int R>
+struct OddRoots;
+template <>
+struct OddRoots<3> {
+  static constexpr double c[1] = {-0.5};
+  static constexpr double s[1] = {0.86602540378443864676};
+};
+template <>
+struct OddRoots<5> {
+  static constexpr double c[2] = {0.30901699437494742410, -0.80901699437494742410};
+  static constexpr double s[2] = {0.95105651629515357212, 0.58778525229247312917};
+};
+template <>
+struct OddRoots<7> {
+  static constexpr double c[3] = {0.62348980185873353053, -0.22252093395631440429,
+                                  -0.90096886790241912624};
+  static constexpr double s[3] = {0.78183148246802980871, 0.97492791218182360702,
+                                  0.43388373911755812048};
+};
+
+template <int R, int S, typename T>
+struct OddDft {
+  __device__ __forceinline__ static void run(cpx<T>* v) {
+    constexpr int H = (R - 1) / 2;
+    cpx<T> a[H], d[H];
+#pragma unroll
+    for (int r = 1; r <= H; ++r) {
+      a[r - 1] = cadd(v[r], v[R - r]);
+      d[r - 1] = csub(v[r], v[R - r]);
+    }
+    cpx<T> out[R];
+    cpx<T> s0 = v[0];
+#pragma unroll
+    for (int r = 0; r < H; ++r) s0 = cadd(s0, a[r]);
+    out[0] = s0;
+#pragma unroll
+    for (int q = 1; q <= H; ++q) {
+      cpx<T> re = v[0], im = {T(0), T(0)};
+#pragma unroll
+      for (int r = 1; r <= H; ++r) {
+        const int e = (r * q) % R;  // angle index; cos even, sin odd in e
+        const int ee = e <= H ? e : R - e;
+        const T cc = T(OddRoots<R>::c[ee - 1]);
+        const T ss = T(e <= H ? OddRoots<R>::s[ee - 1] : -OddRoots<R>::s[ee - 1]);
+        re.x += cc * a[r - 1].x;
+        re.y += cc * a[r - 1].y;
+        im.x += ss * d[r - 1].x;
+        im.y += ss * d[r - 1].y;
+      }
+      // out[q] = re + S i im, out[R-q] = re - S i im
+      const cpx<T> sim = mul_si<S>(im);
+      out[q] = cadd(re, sim);
+      out[R - q] = csub(re, sim);
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) v[q] = out[q];
+  }
+};
+template <int S, typename T>
+struct SmallDft<3, S, T> : OddDft<3, S, T> {};
+template <int S, typename T>
+struct SmallDft<5, S, T> : OddDft<5, S, T> {};
+template <int S, typename T>
+struct SmallDft<7, S, T> : OddDft<7, S, T> {};
+
+
+// radix 16 = 4 x 4 with the inner twiddles W16^(n2 k1)
+template <int S, typename T>
+struct SmallDft<16, S, T> {
+  __device__ __forceinline__ static void run(cpx<T>* v) {
+    // cos / sin of 2 pi e / 16, e = 0..15
+    constexpr double C[16] = {1.0, 0.92387953251128675613, 0.70710678118654752440,
+                              0.38268343236508977173, 0.0, -0.38268343236508977173,
+                              -0.70710678118654752440, -0.92387953251128675613, -1.0,
+                              -0.92387953251128675613, -0.70710678118654752440,
+                              -0.38268343236508977173, 0.0, 0.38268343236508977173,
+                              0.70710678118654752440, 0.92387953251128675613};
+    constexpr double Sn[16] = {0.0, 0.38268343236508977173, 0.70710678118654752440,
+                               0.92387953251128675613, 1.0, 0.92387953251128675613,
+                               0.70710678118654752440, 0.38268343236508977173, 0.0,
+                               -0.38268343236508977173, -0.70710678118654752440,
+                               -0.92387953251128675613, -1.0, -0.92387953251128675613,
+                               -0.70710678118654752440, -0.38268343236508977173};
+    cpx<T> a[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+      cpx<T> col[4] = {v[n2], v[4 + n2], v[8 + n2], v[12 + n2]};
+      SmallDft<4, S, T>::run(col);
+#pragma unroll
+      for (int k1 = 0; k1 < 4; ++k1) {
+        const int e = n2 * k1;
+        if (e == 0) {
+          a[n2][k1] = col[k1];
+        } else {
+          const cpx<T> w = {T(C[e]), T(S * Sn[e])};
+          a[n2][k1] = cmul(col[k1], w);
+        }
+      }
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      cpx<T> row[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+      SmallDft<4, S, T>::run(row);
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = row[k2];
+    }
+  }
+};
+
+constexpr int gather_of(int k) {
+  return (k == K_C2C_F || k == K_C2C_I || k == K_F_C2C || k == K_F_CURL) ? G_CPLX
+         : (k == K_R2C || k == K_F_R2C)                                   ? G_REAL2
+         : (k == K_C2R)                                                    ? G_HERM2
+                                                                           : G_R2R;
+}
+constexpr int scatter_of(int k) {
+  return k == K_C2C_F || k == K_C2C_I ? S_CPLX : k == K_R2C ? S_R2C2 : k == K_C2R ? S_REAL2 : S_R2R;
+}
+constexpr bool in_cplx_of(int k) {
+  return k == K_C2C_F || k == K_C2C_I || k == K_C2R || k == K_F_C2C || k == K_F_CURL;
+}
+constexpr bool fused_of(int k) { return k >= K_F_C2C; }
+
+template <typename T>
+struct Prec {
+  static constexpr int RMAX = max_radix((int)sizeof(T));
+};
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, uint64_t mag) {
+  return (uint32_t)(((uint64_t)n * mag) >> 32);
+}
+
+// ---------------------------------------------------------------------------------
+// One Stockham radix-R stage over F lines of length M held in LDS (line stride ls).
+// Butterfly t of a line reads x[t + r M/R], twiddles by W_{Ns R}^{(t mod Ns) r}, and
+// writes to (t - t mod Ns) R + t mod Ns + q Ns.  The first stage reads through
+// `load` (the gather), later stages read LDS.  Runtime-length form: twiddles from the
+// 4M table; compile-time form: M, R, Ns are constants and twiddles come from the
+// per-stage table (contiguous per butterfly).
+// ---------------------------------------------------------------------------------
+template <typename T, int EL, int R, int S, class Load>
+__device__ __forceinline__ void fft_stage(cpx<T>* buf, int ls, int F, int M, int Ns,
+                                          const cpx<T>* __restrict__ tw, Load& load) {
+  constexpr int NB = (EL + R - 1) / R;
+  cpx<T> v[NB][R];
+  int lin[NB], tt[NB];
+  const int MR = M / R;
+  const int total = F * MR;
+  const int twstep = 4 * (MR / Ns);  // 4M table: W_{Ns R}^e = tw[4 e M / (Ns R)]
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int u = (int)threadIdx.x + i * kThreads;
+    lin[i] = -1;
+    tt[i] = 0;
+    if (u < total) {
+      const int line = u / MR;
+      const int t = u - line * MR;
+      const int k = t % Ns;
+      lin[i] = line;
+      tt[i] = t;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        cpx<T> a = load(line, t + r * MR);
+        if (r > 0 && k > 0) {
+          cpx<T> w = tw[k * r * twstep];
+          if (S > 0) w.y = -w.y;
+          a = cmul(a, w);
+        }
+        v[i][r] = a;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    if (lin[i] >= 0) {
+      SmallDft<R, S, T>::run(v[i]);
+      const int t = tt[i];
+      const int k = t % Ns;
+      const int base = lin[i] * ls + (t - k) * R + k;
+#pragma unroll
+      for (int q = 0; q < R; ++q) buf[base + q * Ns] = v[i][q];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int M, int R, int Ns, int S, class Load>
+__device__ __forceinline__ void fft_stage_ct(cpx<T>* buf, int ls, int F,
+                                             const cpx<T>* __restrict__ stw, Load& load) {
+  constexpr int NB = (elems_per_thread((int)sizeof(T), M) + R - 1) / R;
+  constexpr int MR = M / R;
+  cpx<T> v[NB][R];
+  int lin[NB], tt[NB];
+  const int total = F * MR;
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int u = (int)threadIdx.x + i * kThreads;
+    lin[i] = -1;
+    tt[i] = 0;
+    if (u < total) {
+      const int line = u / MR;
+      const int t = u - line * MR;
+      lin[i] = line;
+      tt[i] = t;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[i][r] = load(line, t + r * MR);
+      if (Ns > 1) {
+        const int k = t % Ns;
+        const cpx<T>* w = stw + k * (R - 1);
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          cpx<T> ww = w[r - 1];
+          if (S > 0) ww.y = -ww.y;
+          v[i][r] = cmul(v[i][r], ww);
+        }
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    if (lin[i] >= 0) {
+      SmallDft<R, S, T>::run(v[i]);
+      const int t = tt[i];
+      const int k = t % Ns;
+      const int base = lin[i] * ls + (t - k) * R + k;
+#pragma unroll
+      for (int q = 0; q < R; ++q) buf[base + q * Ns] = v[i][q];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int M, int S, int s, int Ns, class Load>
+__device__ __forceinline__ void stages_ct(cpx<T>* buf, int ls, int F, const cpx<T>* stw,
+                                          Load& load) {
+  constexpr int R = radix_at(M, s, Prec<T>::RMAX);
+  if constexpr (R != 0) {
+    fft_stage_ct<T, M, R, Ns, S>(buf, ls, F, stw + stage_table_offset(M, s, Prec<T>::RMAX), load);
+    auto lds = [buf, ls](int line, int idx) { return buf[line * ls + idx]; };
+    stages_ct<T, M, S, s + 1, Ns * R>(buf, ls, F, stw, lds);
+  }
+}
+
+template <typename T, int EL, int S, class Load>
+__device__ __forceinline__ void fft_stage_dispatch(int R, cpx<T>* buf, int ls, int F, int M,
+                                                   int Ns, const cpx<T>* tw, Load& load) {
+  switch (R) {
+    case 8: fft_stage<T, EL, 8, S>(buf, ls, F, M, Ns, tw, load); break;
+    case 4: fft_stage<T, EL, 4, S>(buf, ls, F, M, Ns, tw, load); break;
+    case 2: fft_stage<T, EL, 2, S>(buf, ls, F, M, Ns, tw, load); break;
+    case 3: fft_stage<T, EL, 3, S>(buf, ls, F, M, Ns, tw, load); break;
+    case 5: fft_stage<T, EL, 5, S>(buf, ls, F, M, Ns, tw, load); break;
+    case 7: fft_stage<T, EL, 7, S>(buf, ls, F, M, Ns, tw, load); break;
+    default: break;
+  }
+}
+
+// Full FFT of F lines; result in buf in natural order.  MC = compile-time length or 0.
+template <typename T, int MC, int S, class Load>
+__device__ __forceinline__ void fft_lines(cpx<T>* buf, int ls, int F, const PassDesc& d,
+                                          Load& load0) {
+  if constexpr (MC > 1) {
+    stages_ct<T, MC, S, 0, 1>(buf, ls, F, reinterpret_cast<const cpx<T>*>(d.stw), load0);
+  } else {
+    constexpr int EL = elems_per_thread((int)sizeof(T), MC);
+    const cpx<T>* tw = reinterpret_cast<const cpx<T>*>(d.tw);
+    auto lds = [buf, ls](int line, int idx) { return buf[line * ls + idx]; };
+    int Ns = 1;
+    for (int s = 0; s < d.nstages; ++s) {
+      const int R = d.radix[s];
+      if (s == 0) fft_stage_dispatch<T, EL, S>(R, buf, ls, F, d.M, Ns, tw, load0);
+      else fft_stage_dispatch<T, EL, S>(R, buf, ls, F, d.M, Ns, tw, lds);
+      Ns *= R;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// Gathers: value of slot m of FFT line f, from the raw tile in LDS.
+// ---------------------------------------------------------------------------------
+template <typename T>
+struct GatherCplx {  // complex lines, zero padded beyond n_data
+  const cpx<T>* raw;
+  int rs, n_data;
+  __device__ cpx<T> operator()(int f, int m) const {
+    return m < n_data ? raw[f * rs + m] : cpx<T>{T(0), T(0)};
+  }
+};
+
+template <typename T>
+struct GatherReal2 {  // two real lines packed as re + i im, zero padded
+  const T* raw;
+  int rs, n_data, nl;
+  __device__ cpx<T> operator()(int f, int m) const {
+    if (m >= n_data) return {T(0), T(0)};
+    const int l = 2 * f;
+    const T a = raw[l * rs + m];
+    const T b = (l + 1 < nl) ? raw[(l + 1) * rs + m] : T(0);
+    return {a, b};
+  }
+};
+
+template <typename T>
+struct GatherHerm2 {  // two Hermitian half-spectra -> one full spectrum
+  const cpx<T>* raw;
+  int rs, M, nl;
+  __device__ cpx<T> operator()(int f, int m) const {
+    const int l = 2 * f;
+    const bool hi = 2 * m > M;
+    const int mm = hi ? M - m : m;
+    cpx<T> x1 = raw[l * rs + mm];
+    cpx<T> x2 = (l + 1 < nl) ? raw[(l + 1) * rs + mm] : cpx<T>{T(0), T(0)};
+    if (mm == 0 || 2 * mm == M) {  // modes that are real for real data
+      x1.y = T(0);
+      x2.y = T(0);
+    }
+    if (!hi) return {x1.x - x2.y, x1.y + x2.x};   // X1 + i X2
+    return {x1.x + x2.y, -x1.y + x2.x};           // conj(X1) + i conj(X2)
+  }
+};
+
+__device__ __forceinline__ int r2r_weight(const R2R& r, int p) {
+  return p == r.plo ? r.wlo : (p == r.phi ? r.whi : 2);
+}
+
+template <typename T>
+struct GatherR2R {  // symmetric extension of two real lines, with pre-twiddle
+  const T* raw;
+  int rs, in_n, nl;
+  R2R r;
+  const cpx<T>* tw;  // 4M table
+  __device__ cpx<T> operator()(int f, int m) const {
+    const int M = 2 * r.nh;
+    const int l = 2 * f;
+    const T eps = r.b2 ? T(-1) : T(1);          // wrap factor of a full period
+    const T sigma = r.sin ? -eps : eps;          // sign of the mirrored sample
+    T re = T(0), im = T(0);
+    auto add = [&](int p, T coef) {
+      if (p < r.plo || p > r.phi) return;
+      const int j = r.in_rev ? r.in_base - p : p - r.in_base;
+      if (j < 0 || j >= in_n) return;
+      const T c = coef * T(r2r_weight(r, p)) * T(0.5);
+      re += c * raw[l * rs + j];
+      if (l + 1 < nl) im += c * raw[(l + 1) * rs + j];
+    };
+    if (r.a2 == 0) {
+      if (m == 0) add(0, T(1) + sigma * eps);
+      else if (m == r.nh) add(r.nh, T(1) + sigma);
+      else if (m < r.nh) add(m, T(1));
+      else add(M - m, sigma);
+    } else {
+      if (m < r.nh) add(m, T(1));
+      else add(M - 1 - m, sigma);
+    }
+    cpx<T> z = {re, im};
+    if (r.b2) z = cmul(z, tw[2 * m]);  // exp(-i pi m b / nh), b = 1/2
+    return z;
+  }
+};
+
+// Write the symmetric extensions of a real-to-real tile into the FFT buffer (one LDS
+// pass; the raw tile lives outside the buffer), so that the FFT stages read plain LDS.
+template <typename T, int MC>
+__device__ __forceinline__ void extend_r2r(cpx<T>* buf, int ls, int F, int M, const GatherR2R<T>& g) {
+  const int total = F * M;
+  for (int e = threadIdx.x; e < total; e += kThreads) {
+    const int f = e / M, m = e - f * M;
+    buf[f * ls + m] = g(f, m);
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------------
+// Scatters: value of output element j of tile line l, from the FFT buffer.
+// ---------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T scatter_r2r(const cpx<T>* buf, int ls, const R2R& r,
+                                         const cpx<T>* tw, int l, int j) {
+  const int q = r.out_rev ? r.out_base - j : j + r.out_base;
+  if (q < r.qlo || q > r.qhi) return T(0);
+  cpx<T> Y = buf[(l >> 1) * ls + q];
+  if (r.a2) Y = cmul(Y, tw[2 * q + r.b2]);  // exp(-i pi a (q + b) / nh), a = 1/2
+  if (!r.sin) return (l & 1) ? Y.y : Y.x;
+  return (l & 1) ? Y.x : -Y.y;
+}
+
+// ---------------------------------------------------------------------------------
+// Coalesced tile load / store.  Element e of the tile maps to (line l, index i):
+// line-contiguous data walk along the line (l = e / n), otherwise across the B lines
+// of the tile (i = e / B); divisions use host-computed multipliers.  Loads are issued
+// kUnroll at a time before their LDS writes so that several are in flight.
+// ---------------------------------------------------------------------------------
+constexpr int kUnroll = 4;
+
+template <typename E>
+__device__ __forceinline__ void load_tile(const E* __restrict__ in, int64_t s_line, int64_t s_b,
+                                          int nl, int n, uint64_t mag_n, int B, uint64_t mag_B,
+                                          E* raw, int rs) {
+  if (s_line == 1) {
+    const int total = nl * n;
+    for (int base = threadIdx.x; base < total; base += kUnroll * kThreads) {
+      E v[kUnroll];
+      int dst[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int e = base + u * kThreads;
+        dst[u] = -1;
+        if (e < total) {
+          const int l = (int)fdiv(e, mag_n), i = e - l * n;
+          v[u] = in[l * s_b + i];
+          dst[u] = l * rs + i;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+        if (dst[u] >= 0) raw[dst[u]] = v[u];
+    }
+  } else {
+    const int total = B * n;
+    for (int base = threadIdx.x; base < total; base += kUnroll * kThreads) {
+      E v[kUnroll];
+      int dst[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int e = base + u * kThreads;
+        dst[u] = -1;
+        if (e < total) {
+          const int i = (int)fdiv(e, mag_B), l = e - i * B;
+          if (l < nl) {
+            v[u] = in[l * s_b + (int64_t)i * s_line];
+            dst[u] = l * rs + i;
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+        if (dst[u] >= 0) raw[dst[u]] = v[u];
+    }
+  }
+}
+
+// Store with the output conventions of the batch axes (last pass): `out` points at
+// (c, b0); writes 0 on odd faces and duplicates index 0 to index last when asked.
+template <bool FIX, typename E, class Val>
+__device__ __forceinline__ void store_tile(E* __restrict__ out, int64_t s_line, int64_t s_b,
+                                           int64_t s_c, int nl, int n, uint64_t mag_n, int B,
+                                           uint64_t mag_B, int b0, int c, const Fixup& fx,
+                                           Val& val) {
+  bool czero = false, cdup = false;
+  if (FIX) {
+    czero = (fx.c_zero_lo && c == 0) || (fx.c_zero_hi && c == fx.c_last);
+    cdup = fx.c_dup && c == 0;
+  }
+  const bool lc = (s_line == 1);
+  const int total = lc ? nl * n : B * n;
+  for (int e = threadIdx.x; e < total; e += kThreads) {
+    int l, j;
+    if (lc) {
+      l = (int)fdiv(e, mag_n);
+      j = e - l * n;
+    } else {
+      j = (int)fdiv(e, mag_B);
+      l = e - j * B;
+      if (l >= nl) continue;
+    }
+    E v = val(l, j);
+    const int64_t o = l * s_b + (int64_t)j * s_line;
+    if (FIX) {
+      const int b = b0 + l;
+      if (czero || (fx.b_zero_lo && b == 0) || (fx.b_zero_hi && b == fx.b_last)) v = E{};
+      out[o] = v;
+      const bool bdup = fx.b_dup && b == 0;
+      if (bdup) out[o + (int64_t)fx.b_last * s_b] = v;
+      if (cdup) {
+        out[o + (int64_t)fx.c_last * s_c] = v;
+        if (bdup) out[o + (int64_t)fx.b_last * s_b + (int64_t)fx.c_last * s_c] = v;
+      }
+    } else {
+      out[o] = v;
+    }
+  }
+}
+
+__device__ __forceinline__ int fold_index(int k, int M) {
+  if (M == 0) return k;
+  const int r = M - k;
+  return k < r ? k : r;
+}
+
+template <typename T>
+__device__ __forceinline__ T signed_wave(int k, int M, T dw) {
+  // wavenumber of DFT mode k of length M; the Nyquist mode differentiates to 0
+  if (2 * k == M) return T(0);
+  const int ks = (2 * k > M) ? k - M : k;
+  return dw * T(ks);
+}
+
+struct TileIdx {
+  int b0, c, comp, nl;
+};
+
+__device__ __forceinline__ TileIdx tile_index(const PassDesc& d, int tile) {
+  const int nbt = (d.nb + d.B - 1) / d.B;
+  TileIdx ti;
+  const int bt = tile % nbt;
+  const int t = tile / nbt;
+  ti.c = t % d.nc;
+  ti.comp = t / d.nc;
+  ti.b0 = bt * d.B;
+  ti.nl = min(d.B, d.nb - ti.b0);
+  return ti;
+}
+
+// ---------------------------------------------------------------------------------
+// Plain pass on one tile
+// ---------------------------------------------------------------------------------
+template <typename T, int MC, bool FIX, class Val>
+__device__ __forceinline__ void store_real(const PassDesc& d, void* out, const TileIdx& ti,
+                                           int64_t out_off, Val& val) {
+  store_tile<FIX>(reinterpret_cast<T*>(out) + out_off, d.out_s_line, d.out_s_b, d.out_s_c, ti.nl,
+                  d.out_n, d.mag_out, d.B, d.mag_B, ti.b0, ti.c, d.fix, val);
+}
+
+template <typename T, int MC, int KIND>
+__device__ void plain_compute(const PassDesc& d, void* out, const TileIdx& ti, char* smem) {
+  const int gather = KIND == K_ANY ? d.gather : gather_of(KIND);
+  const int scatter = KIND == K_ANY ? d.scatter : scatter_of(KIND);
+  const int sign = KIND == K_ANY ? d.sign : (KIND == K_C2C_I || KIND == K_C2R ? +1 : -1);
+  const int nl = ti.nl;
+  const cpx<T>* tw = reinterpret_cast<const cpx<T>*>(d.tw);
+  const int M = MC > 1 ? MC : d.M;
+  const int ls = M + 1;
+  cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem);
+  const int64_t out_off = ti.comp * d.out_s_comp + ti.c * d.out_s_c + ti.b0 * d.out_s_b;
+  const int rs = d.in_n + 1;
+
+  // 2) FFT (first stage gathers from the raw tile, which aliases the FFT buffer)
+  const int F = (gather == G_CPLX) ? nl : (nl + 1) / 2;
+  if (gather == G_CPLX) {
+    GatherCplx<T> g{reinterpret_cast<const cpx<T>*>(smem), rs, d.n_data};
+    if (sign < 0) fft_lines<T, MC, -1>(buf, ls, F, d, g);
+    else fft_lines<T, MC, +1>(buf, ls, F, d, g);
+  } else if (gather == G_REAL2) {
+    GatherReal2<T> g{reinterpret_cast<const T*>(smem), rs, d.n_data, nl};
+    fft_lines<T, MC, -1>(buf, ls, F, d, g);
+  } else if (gather == G_HERM2) {
+    GatherHerm2<T> g{reinterpret_cast<const cpx<T>*>(smem), rs, M, nl};
+    fft_lines<T, MC, +1>(buf, ls, F, d, g);
+  } else {
+    GatherR2R<T> g{reinterpret_cast<const T*>(smem + d.raw_off), rs, d.in_n, nl, d.r2r, tw};
+    extend_r2r<T, MC>(buf, ls, F, M, g);
+    auto lds = [buf, ls](int line, int idx) { return buf[line * ls + idx]; };
+    fft_lines<T, MC, -1>(buf, ls, F, d, lds);
+  }
+
+  // 3) write the lines into the output layout
+  if (scatter == S_CPLX) {
+    auto val = [&](int l, int j) { return buf[l * ls + (j < M ? j : j - M)]; };
+    store_tile<false>(reinterpret_cast<cpx<T>*>(out) + out_off, d.out_s_line, d.out_s_b, d.out_s_c,
+                      nl, d.out_n, d.mag_out, d.B, d.mag_B, ti.b0, ti.c, d.fix, val);
+  } else if (scatter == S_R2C2) {
+    auto val = [&](int l, int k) {
+      const cpx<T>* z = buf + (l >> 1) * ls;
+      const cpx<T> zk = z[k], zm = z[k == 0 ? 0 : M - k];
+      if (l & 1) return cpx<T>{T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x)};
+      return cpx<T>{T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
+    };
+    store_tile<false>(reinterpret_cast<cpx<T>*>(out) + out_off, d.out_s_line, d.out_s_b, d.out_s_c,
+                      nl, d.out_n, d.mag_out, d.B, d.mag_B, ti.b0, ti.c, d.fix, val);
+  } else if (scatter == S_REAL2) {
+    auto val = [&](int l, int j) {
+      const cpx<T> z = buf[(l >> 1) * ls + (j < M ? j : j - M)];
+      return (l & 1) ? z.y : z.x;
+    };
+    if (d.has_fix) store_real<T, MC, true>(d, out, ti, out_off, val);
+    else store_real<T, MC, false>(d, out, ti, out_off, val);
+  } else {
+    auto val = [&](int l, int j) { return scatter_r2r<T>(buf, ls, d.r2r, tw, l, j); };
+    if (d.has_fix) store_real<T, MC, true>(d, out, ti, out_off, val);
+    else store_real<T, MC, false>(d, out, ti, out_off, val);
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// Fused pass 3 on one tile: forward FFT, spectral multiply, inverse FFT.
+// ---------------------------------------------------------------------------------
+template <typename T, int MC, int KIND>
+__device__ void fused_compute(const PassDesc& d, void* out, const TileIdx& ti, char* smem) {
+  const int gather = KIND == K_ANY ? d.gather : gather_of(KIND);
+  const bool curl = KIND == K_ANY ? (d.g.curl != 0) : (KIND == K_F_CURL);
+  const int nl = ti.nl, b0 = ti.b0, c = ti.c, comp = ti.comp;  // curl: comp = 0
+  const cpx<T>* tw = reinterpret_cast<const cpx<T>*>(d.tw);
+  const int M = MC > 1 ? MC : d.M;
+  const int ls = M + 1;
+  cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem);
+  const int rs = d.in_n + 1;
+  const int ncl = curl ? 3 : 1;   // components held by the tile
+  const T* G = reinterpret_cast<const T*>(d.g.G);
+  const int fc = fold_index(c, d.g.fold_c);
+  const Fixup nofix{};
+
+  if (gather == G_R2R) {
+    // ---- all-real-to-real problem: forward R2R -> spectrum in LDS -> inverse R2R
+    const int F = (nl + 1) / 2;
+    auto lds = [buf, ls](int line, int idx) { return buf[line * ls + idx]; };
+    {
+      GatherR2R<T> g{reinterpret_cast<const T*>(smem + d.raw_off), rs, d.in_n, nl, d.r2r, tw};
+      extend_r2r<T, MC>(buf, ls, F, M, g);
+      fft_lines<T, MC, -1>(buf, ls, F, d, lds);
+    }
+    // spectrum (real) into its own LDS region (where the raw tile was), times the
+    // Green's spectrum
+    const int ss = d.spec_n + 1;
+    T* spec = reinterpret_cast<T*>(smem + d.raw_off);
+    for (int e = threadIdx.x; e < nl * d.spec_n; e += kThreads) {
+      const int l = (int)fdiv(e, d.mag_spec), j = e - l * d.spec_n;
+      const T g = G[((int64_t)fc * d.g.F_b + fold_index(b0 + l, d.g.fold_b)) * d.g.F_line +
+                    fold_index(j, d.g.fold_line)];
+      spec[l * ss + j] = g * scatter_r2r<T>(buf, ls, d.r2r, tw, l, j);
+    }
+    __syncthreads();
+    {
+      GatherR2R<T> g{spec, ss, d.spec_n, nl, d.r2r2, tw};
+      extend_r2r<T, MC>(buf, ls, F, M, g);
+      fft_lines<T, MC, -1>(buf, ls, F, d, lds);
+    }
+    const int64_t out_off = comp * d.out_s_comp + c * d.out_s_c + b0 * d.out_s_b;
+    auto val = [&](int l, int j) { return scatter_r2r<T>(buf, ls, d.r2r2, tw, l, j); };
+    store_tile<false>(reinterpret_cast<T*>(out) + out_off, d.out_s_line, d.out_s_b, d.out_s_c, nl,
+                      d.out_n, d.mag_out, d.B, d.mag_B, b0, c, nofix, val);
+    return;
+  }
+
+  if (gather == G_REAL2) {
+    // ---- only DFT axis of the problem: two real lines per FFT
+    const int F = (nl + 1) / 2;
+    GatherReal2<T> g{reinterpret_cast<const T*>(smem), rs, d.n_data, nl};
+    fft_lines<T, MC, -1>(buf, ls, F, d, g);
+    // The two packed lines have their own Green rows: split Z into the two Hermitian
+    // spectra X1 = (Z_k + conj Z_{M-k})/2, X2 = (Z_k - conj Z_{M-k})/(2i), scale each
+    // by its (real, even) row, and pack again as Y1 + i Y2.  One thread owns the pair
+    // (k, M-k).
+    const int H = M / 2 + 1;
+    for (int e = threadIdx.x; e < F * H; e += kThreads) {
+      const int f = e / H, k = e - f * H;
+      const int kk = fold_index(k, d.g.fold_line);
+      const int l0 = 2 * f, l1 = min(2 * f + 1, nl - 1);
+      const T g0 = G[((int64_t)fc * d.g.F_b + fold_index(b0 + l0, d.g.fold_b)) * d.g.F_line + kk];
+      const T g1 = G[((int64_t)fc * d.g.F_b + fold_index(b0 + l1, d.g.fold_b)) * d.g.F_line + kk];
+      const int km = (k == 0) ? 0 : M - k;
+      const cpx<T> zk = buf[f * ls + k], zm = buf[f * ls + km];
+      const cpx<T> x1 = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
+      const cpx<T> x2 = {T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x)};
+      // Z'_k = g0 X1 + i g1 X2 ;  Z'_{M-k} = g0 conj(X1) + i g1 conj(X2)
+      buf[f * ls + k] = {g0 * x1.x - g1 * x2.y, g0 * x1.y + g1 * x2.x};
+      if (km != k) buf[f * ls + km] = {g0 * x1.x + g1 * x2.y, -g0 * x1.y + g1 * x2.x};
+    }
+    __syncthreads();
+    auto lds = [buf, ls](int line, int idx) { return buf[line * ls + idx]; };
+    fft_lines<T, MC, +1>(buf, ls, F, d, lds);
+    const int64_t out_off = comp * d.out_s_comp + c * d.out_s_c + b0 * d.out_s_b;
+    auto val = [&](int l, int j) {
+      const cpx<T> z = buf[(l >> 1) * ls + (j < M ? j : j - M)];
+      return (l & 1) ? z.y : z.x;
+    };
+    store_tile<false>(reinterpret_cast<T*>(out) + out_off, d.out_s_line, d.out_s_b, d.out_s_c, nl,
+                      d.out_n, d.mag_out, d.B, d.mag_B, b0, c, nofix, val);
+    return;
+  }
+
+  // ---- complex lines (C2C along the last axis), one or three components
+  const int F = ncl * nl;
+  {
+    GatherCplx<T> g{reinterpret_cast<const cpx<T>*>(smem), rs, d.n_data};
+    fft_lines<T, MC, -1>(buf, ls, F, d, g);
+  }
+  if (!curl) {
+    for (int e = threadIdx.x; e < nl * M; e += kThreads) {
+      const int l = e / M, k = e - l * M;
+      const T g = G[((int64_t)fc * d.g.F_b + fold_index(b0 + l, d.g.fold_b)) * d.g.F_line +
+                    fold_index(k, d.g.fold_line)];
+      cpx<T> z = buf[l * ls + k];
+      z.x *= g;
+      z.y *= g;
+      buf[l * ls + k] = z;
+    }
+  } else {
+    const T wc = signed_wave<T>(c, d.g.M_c, T(d.g.dw_c));
+    const T dwl = T(d.g.dw_line), dwb = T(d.g.dw_b);
+    for (int e = threadIdx.x; e < nl * M; e += kThreads) {
+      const int l = e / M, k = e - l * M;
+      const T g = G[((int64_t)fc * d.g.F_b + fold_index(b0 + l, d.g.fold_b)) * d.g.F_line +
+                    fold_index(k, d.g.fold_line)];
+      const T wl = signed_wave<T>(k, d.g.M_line, dwl);
+      const T wb = signed_wave<T>(b0 + l, d.g.M_b, dwb);
+      const T wx = d.g.axis_line == 0 ? wl : (d.g.axis_b == 0 ? wb : wc);
+      const T wy = d.g.axis_line == 1 ? wl : (d.g.axis_b == 1 ? wb : wc);
+      const T wz = d.g.axis_line == 2 ? wl : (d.g.axis_b == 2 ? wb : wc);
+      const cpx<T> fx = buf[(0 * nl + l) * ls + k];
+      const cpx<T> fy = buf[(1 * nl + l) * ls + k];
+      const cpx<T> fz = buf[(2 * nl + l) * ls + k];
+      // u_hat = G * i (w x f_hat)
+      const cpx<T> cx = {wy * fz.x - wz * fy.x, wy * fz.y - wz * fy.y};
+      const cpx<T> cy = {wz * fx.x - wx * fz.x, wz * fx.y - wx * fz.y};
+      const cpx<T> cz = {wx * fy.x - wy * fx.x, wx * fy.y - wy * fx.y};
+      buf[(0 * nl + l) * ls + k] = {-g * cx.y, g * cx.x};
+      buf[(1 * nl + l) * ls + k] = {-g * cy.y, g * cy.x};
+      buf[(2 * nl + l) * ls + k] = {-g * cz.y, g * cz.x};
+    }
+  }
+  __syncthreads();
+  {
+    auto lds = [buf, ls](int line, int idx) { return buf[line * ls + idx]; };
+    fft_lines<T, MC, +1>(buf, ls, F, d, lds);
+  }
+  for (int q = 0; q < ncl; ++q) {
+    const int cc = curl ? q : comp;
+    const int64_t out_off = cc * d.out_s_comp + c * d.out_s_c + b0 * d.out_s_b;
+    const cpx<T>* z = buf + (size_t)q * nl * ls;
+    auto val = [&](int l, int j) { return z[l * ls + (j < M ? j : j - M)]; };
+    store_tile<false>(reinterpret_cast<cpx<T>*>(out) + out_off, d.out_s_line, d.out_s_b, d.out_s_c,
+                      nl, d.out_n, d.mag_out, d.B, d.mag_B, b0, c, nofix, val);
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// Input staging: a tile's input is read from global memory into registers (`fetch`),
+// then written to the raw LDS region (`commit`).  Element e of the tile walks along
+// the lines when they are contiguous, else across the B lines of the tile; the fused
+// Biot-Savart pass reads the three components of the same lines (component q's lines
+// follow component q-1's in LDS).
+// ---------------------------------------------------------------------------------
+// Values per thread held by the register stage of one tile (per component).
+template <typename T, typename E, int NCL, int MC>
+struct StageCount {
+  static constexpr int U = stage_values((int)sizeof(T), MC, sizeof(E) != sizeof(T), NCL);
+};
+
+struct TileWalk {
+  int per, n, B, nl;
+  bool lc;
+  uint64_t mag_n, mag_B;
+  // element r of one component -> line l, index i; false when outside the tile
+  __device__ __forceinline__ bool at(int r, int& l, int& i) const {
+    if (r >= per) return false;
+    if (lc) {
+      l = (int)fdiv(r, mag_n);
+      i = r - l * n;
+    } else {
+      i = (int)fdiv(r, mag_B);
+      l = r - i * B;
+      if (l >= nl) return false;
+    }
+    return true;
+  }
+};
+
+__device__ __forceinline__ TileWalk in_walk(const PassDesc& d, const TileIdx& ti) {
+  TileWalk w;
+  w.lc = (d.in_s_line == 1);
+  w.n = d.in_n;
+  w.B = d.B;
+  w.nl = ti.nl;
+  w.per = w.lc ? ti.nl * d.in_n : d.B * d.in_n;
+  w.mag_n = d.mag_in;
+  w.mag_B = d.mag_B;
+  return w;
+}
+
+// Register stage of one thread: complex values are held as two real arrays (a 16-byte
+// struct array is not always promoted to registers).
+template <typename T, typename E, int N>
+struct RegStage {
+  T a[N];
+  __device__ __forceinline__ void set(int k, const T& v) { a[k] = v; }
+  __device__ __forceinline__ T get(int k) const { return a[k]; }
+};
+template <typename T, int N>
+struct RegStage<T, cpx<T>, N> {
+  T x[N], y[N];
+  __device__ __forceinline__ void set(int k, const cpx<T>& v) {
+    x[k] = v.x;
+    y[k] = v.y;
+  }
+  __device__ __forceinline__ cpx<T> get(int k) const { return {x[k], y[k]}; }
+};
+
+// Global -> registers.  Addresses are a uniform 64-bit base per component plus a 32-bit
+// byte offset per element; the planner sends tiles that span 4 GiB or more to the
+// runtime-length kernels (OFF64), which use 64-bit offsets.
+template <int U, int NCL, bool OFF64, typename E, class Stage>
+__device__ __forceinline__ void fetch(Stage& v, const PassDesc& d, const void* in, const TileIdx& ti) {
+  const TileWalk w = in_walk(d, ti);
+  const int comp0 = NCL == 3 ? 0 : ti.comp;
+#pragma unroll
+  for (int q = 0; q < NCL; ++q) {
+    const char* base = reinterpret_cast<const char*>(in) +
+                       ((int64_t)(comp0 + q) * d.in_s_comp + (int64_t)ti.c * d.in_s_c +
+                        (int64_t)ti.b0 * d.in_s_b) * (int64_t)sizeof(E);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      int l, i;
+      if (w.at((int)threadIdx.x + u * kThreads, l, i)) {
+        if constexpr (OFF64) {
+          const int64_t off = ((int64_t)l * d.in_s_b + (int64_t)i * d.in_s_line) * (int64_t)sizeof(E);
+          v.set(q * U + u, *reinterpret_cast<const E*>(base + off));
+        } else {
+          const uint32_t off = ((uint32_t)l * (uint32_t)d.in_s_b + (uint32_t)i * (uint32_t)d.in_s_line) *
+                               (uint32_t)sizeof(E);
+          v.set(q * U + u, *reinterpret_cast<const E*>(base + off));
+        }
+      }
+    }
+  }
+}
+
+// Registers -> raw LDS tile; component q's lines follow component q-1's.
+template <int U, int NCL, typename E, class Stage>
+__device__ __forceinline__ void commit(const Stage& v, const PassDesc& d, const TileIdx& ti,
+                                       char* smem) {
+  const TileWalk w = in_walk(d, ti);
+  E* raw = reinterpret_cast<E*>(smem + d.raw_off);
+  const int rs = d.in_n + 1;
+#pragma unroll
+  for (int q = 0; q < NCL; ++q) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      int l, i;
+      if (w.at((int)threadIdx.x + u * kThreads, l, i)) raw[(q * ti.nl + l) * rs + i] = v.get(q * U + u);
+    }
+  }
+}
+
+template <typename T, int MC, int KIND>
+__device__ __forceinline__ void compute(const PassDesc& d, void* out, const TileIdx& ti,
+                                        char* smem) {
+  if constexpr (KIND == K_ANY) {
+    if (d.fused) fused_compute<T, MC, K_ANY>(d, out, ti, smem);
+    else plain_compute<T, MC, K_ANY>(d, out, ti, smem);
+  } else if constexpr (fused_of(KIND)) {
+    fused_compute<T, MC, KIND>(d, out, ti, smem);
+  } else {
+    plain_compute<T, MC, KIND>(d, out, ti, smem);
+  }
+}
+
+// One tile, no pipelining (batched launches: the kind is read from the descriptor).
+template <typename T, int MC, typename E, int NCL>
+__device__ __forceinline__ void run_tile_e(const PassDesc& d, const void* in, void* out, int tile,
+                                           char* smem) {
+  constexpr int U = StageCount<T, E, NCL, MC>::U;
+  RegStage<T, E, U * NCL> v;
+  const TileIdx ti = tile_index(d, tile);
+  fetch<U, NCL, (MC <= 1), E>(v, d, in, ti);
+  commit<U, NCL, E>(v, d, ti, smem);
+  __syncthreads();
+  compute<T, MC, K_ANY>(d, out, ti, smem);
+}
+
+template <typename T, int MC>
+__device__ __forceinline__ void run_tile(const PassDesc& d, const void* in, void* out, int tile,
+                                         char* smem) {
+  if (d.fused && d.g.curl) run_tile_e<T, MC, cpx<T>, 3>(d, in, out, tile, smem);
+  else if (d.in_cplx) run_tile_e<T, MC, cpx<T>, 1>(d, in, out, tile, smem);
+  else run_tile_e<T, MC, T, 1>(d, in, out, tile, smem);
+}
+
+// Persistent loop over the tiles of a pass: while tile t is transformed in LDS, the
+// input of the next tile of this workgroup is already on its way into registers.
+template <typename T, int MC, int KIND>
+__device__ __forceinline__ void run_pipelined(const PassDesc& d, const void* in, void* out,
+                                              char* smem) {
+  using E = typename std::conditional<in_cplx_of(KIND), cpx<T>, T>::type;
+  constexpr int NCL = KIND == K_F_CURL ? 3 : 1;
+  constexpr int U = StageCount<T, E, NCL, MC>::U;
+  int tile = blockIdx.x;
+  const int stride = gridDim.x;
+  if (tile >= d.tiles) return;
+  RegStage<T, E, U * NCL> v;
+  TileIdx ti = tile_index(d, tile);
+  fetch<U, NCL, false, E>(v, d, in, ti);
+  while (true) {
+    __syncthreads();  // the previous tile's LDS reads are finished
+    commit<U, NCL, E>(v, d, ti, smem);
+    __syncthreads();
+    const int next = tile + stride;
+    TileIdx tn = ti;
+    if (next < d.tiles) {
+      tn = tile_index(d, next);
+      fetch<U, NCL, false, E>(v, d, in, tn);
+    }
+    compute<T, MC, KIND>(d, out, ti, smem);
+    if (next >= d.tiles) break;
+    tile = next;
+    ti = tn;
+  }
+}
+
+// Tile of a block.  Workgroups are dispatched round-robin over the 8 XCDs; with `xcd`
+// set, consecutive tiles (neighbours in memory along the tile axis) are given to
+// blocks of one XCD so that they share its L2.  The grid then has 8 * ceil(tiles / 8)
+// blocks and the surplus ones exit.
+__device__ __forceinline__ int block_tile(int xcd, int tiles) {
+  const int b = blockIdx.x;
+  if (!xcd) return b;
+  const int per = (tiles + 7) / 8;
+  return (b & 7) * per + (b >> 3);
+}
+
+// The descriptor lives in device memory (uniform loads); the buffers of this solve are
+// kernel arguments.
+template <typename T, int MC, int KIND>
+__global__ __launch_bounds__(kThreads) void pass_kernel(const PassDesc* __restrict__ dp,
+                                                        const void* in, void* out) {
+  extern __shared__ __align__(16) char smem[];
+  if constexpr (!pipelined_kernel((int)sizeof(T), MC)) {
+    // runtime lengths and long FP64 lines: one tile per workgroup, no register prefetch
+    const PassDesc& d = *dp;
+    if ((int)blockIdx.x >= d.tiles) return;
+    using E = typename std::conditional<in_cplx_of(KIND), cpx<T>, T>::type;
+    constexpr int NCL = KIND == K_F_CURL ? 3 : 1;
+    constexpr int U = StageCount<T, E, NCL, MC>::U;
+    RegStage<T, E, U * NCL> v;
+    const TileIdx ti = tile_index(d, blockIdx.x);
+    fetch<U, NCL, (MC <= 1), E>(v, d, in, ti);
+    commit<U, NCL, E>(v, d, ti, smem);
+    __syncthreads();
+    compute<T, MC, KIND>(d, out, ti, smem);
+  } else {
+    run_pipelined<T, MC, KIND>(*dp, in, out, smem);
+  }
+}
+
+// Batched form: tiles of many descriptors of one length class in one launch;
+// prefix[i] = first tile of descriptor i, prefix[n] = total.
+template <typename T, int MC>
+__global__ __launch_bounds__(kThreads) void pass_kernel_batched(const PassDesc* __restrict__ ds,
+                                                                const int* __restrict__ prefix,
+                                                                int n) {
+  extern __shared__ __align__(16) char smem[];
+  const int tile = blockIdx.x;
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= tile) lo = mid;
+    else hi = mid - 1;
+  }
+  const PassDesc& d = ds[lo];
+  run_tile<T, MC>(d, d.in, d.out, tile - prefix[lo], smem);
+}
+
+
+}  // namespace fm

@@ -1,0 +1,246 @@
+// FP64 generation kernels (twiddles, Green's spectrum) and the length dispatch of the
+// pass launchers.
+#include <hip/hip_runtime.h>
+
+#include "fm_device.h"
+#include "fm_launch.h"
+
+namespace fm {
+
+// ---------------------------------------------------------------------------------
+// FP64 generation: twiddles, Green's spectrum samples, finalisation
+// ---------------------------------------------------------------------------------
+// Per-stage twiddles of a compile-time length: stage s (radix R, Ns = product of the
+// earlier radices) holds W_{Ns R}^{k r} = exp(-2 pi i k r / (Ns R)) at
+// offset(s) + k (R - 1) + r - 1, for k < Ns and 1 <= r < R.
+template <typename T>
+__global__ void stage_twiddle_kernel(cpx<T>* out, int M) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  int off = 0, ns = 1;
+  for (int s = 0;; ++s) {
+    const int R = radix_at(M, s, max_radix((int)sizeof(T)));
+    if (R == 0) return;
+    const int n = ns * (R - 1);
+    if (j < off + n) {
+      const int e = j - off;
+      const int k = e / (R - 1), r = e % (R - 1) + 1;
+      const long long num = 2LL * k * r;  // angle 2 pi k r / (ns R) = pi * num / (ns R)
+      double sn, cs;
+      sincospi((double)(num % (2LL * ns * R)) / (double)(ns * R), &sn, &cs);
+      out[j] = {T(cs), T(-sn)};
+      return;
+    }
+    off += n;
+    ns *= R;
+  }
+}
+
+template <typename T>
+__global__ void twiddle_kernel(cpx<T>* out, int M) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= 4 * M) return;
+  double s, c;
+  sincospi((double)j / (2.0 * (double)M), &s, &c);  // angle 2 pi j / (4 M)
+  out[j] = {T(c), T(-s)};
+}
+
+// K_nu(x) for nu = 0, 1 from K_nu(x) = int_0^inf exp(-x cosh t) cosh(nu t) dt: the
+// trapezoidal rule on this doubly-exponentially decaying analytic integrand converges
+// geometrically (step 0.1 gives full double precision for the x used here); for large
+// x the asymptotic expansion sqrt(pi/2x) e^-x sum_k a_k(nu) / x^k is used instead.
+__device__ double bessel_k(int nu, double x) {
+  if (x >= 25.0) {
+    const double mu = 4.0 * nu * nu;
+    double term = 1.0, sum = 1.0;
+    for (int k = 1; k <= 30; ++k) {
+      term *= (mu - (2.0 * k - 1.0) * (2.0 * k - 1.0)) / (k * 8.0 * x);
+      sum += term;
+      if (fabs(term) < 1e-17 * fabs(sum)) break;
+    }
+    return sqrt(3.14159265358979323846 / (2.0 * x)) * exp(-x) * sum;
+  }
+  const double h = 0.1;
+  // terms scaled by exp(x) to avoid underflow for larger x
+  double sum = 0.5;  // t = 0: exp(-x (cosh 0 - 1)) cosh(0) = 1, half weight
+  for (int j = 1; j < 2000; ++j) {
+    const double tj = j * h;
+    const double ch = cosh(tj);
+    const double ex = x * (ch - 1.0);
+    if (ex > 45.0 + tj) break;
+    sum += exp(-ex) * (nu ? ch : 1.0);
+  }
+  return h * sum * exp(-x);
+}
+
+
+
+__device__ double green_value(const GreenGen& g, double rho, double k) {
+  const double pi = 3.14159265358979323846;
+  if (g.du == 3) {
+    if (rho > 0.0) return -1.0 / (4.0 * pi * rho);
+    const double s = -3.0 / (8.0 * pi * g.r_eq);
+    return g.variant == 0 ? s * g.cellvol : s;
+  }
+  if (g.du == 2) {
+    if (k == 0.0) {
+      if (rho > 0.0) return log(rho) / (2.0 * pi);
+      return (pi - 6.0 + 2.0 * log(pi * g.r_eq * g.r_eq / 2.0)) / (8.0 * pi);
+    }
+    if (rho > 0.0) return -bessel_k(0, k * rho) / (2.0 * pi);
+    const double x = k * g.r_eq;
+    return -(1.0 - x * bessel_k(1, x)) / (pi * x * x);
+  }
+  if (g.du == 1) {
+    if (k == 0.0) return 0.5 * rho;
+    return -exp(-k * rho) / (2.0 * k);
+  }
+  return k == 0.0 ? 0.0 : -1.0 / (k * k);
+}
+
+__global__ void green_sample_kernel(double* S, GreenGen g) {
+  const int64_t total = (int64_t)g.n[0] * g.n[1] * g.n[2];
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  int idx[3];
+  int64_t r = e;
+  idx[2] = (int)(r % g.n[2]);
+  r /= g.n[2];
+  idx[1] = (int)(r % g.n[1]);
+  idx[0] = (int)(r / g.n[1]);
+  double r2 = 0.0, k2 = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    if (g.unb[a]) {
+      const double dd = idx[a] * g.h[a];
+      r2 += dd * dd;
+    } else {
+      const double w = g.dw[a] * (idx[a] + g.shift[a]);
+      k2 += w * w;
+    }
+  }
+  S[e] = green_value(g, sqrt(r2), sqrt(k2));
+}
+
+// table[f] = scale * S[f + off] (per axis offsets), converted to T
+template <typename T>
+__global__ void green_final_kernel(T* G, const double* S, int F0, int F1, int F2, int n1, int n2,
+                                   int o0, int o1, int o2, double scale) {
+  const int64_t total = (int64_t)F0 * F1 * F2;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  int64_t r = e;
+  const int f2 = (int)(r % F2);
+  r /= F2;
+  const int f1 = (int)(r % F1);
+  const int f0 = (int)(r / F1);
+  const int64_t s = ((int64_t)(f0 + o0) * n1 + (f1 + o1)) * n2 + (f2 + o2);
+  G[e] = T(scale * S[s]);
+}
+
+}  // namespace fm
+
+
+// ---------------------------------------------------------------------------------
+// Host launchers (internal to the library)
+// ---------------------------------------------------------------------------------
+namespace fm {
+
+bool is_fast_len(int M) {
+  for (int m : kFastLens)
+    if (m == M) return true;
+  return false;
+}
+
+#define FM_LEN_CASES(T, CALL)       \
+  case 32: return CALL(T, 32);      \
+  case 48: return CALL(T, 48);      \
+  case 64: return CALL(T, 64);      \
+  case 96: return CALL(T, 96);      \
+  case 128: return CALL(T, 128);    \
+  case 192: return CALL(T, 192);    \
+  case 256: return CALL(T, 256);    \
+  case 384: return CALL(T, 384);    \
+  case 512: return CALL(T, 512);    \
+  case 768: return CALL(T, 768);    \
+  case 1024: return CALL(T, 1024);  \
+  case 2048: return CALL(T, 2048);  \
+  case 4096: return CALL(T, 4096);
+
+template <typename T>
+hipError_t launch_pass(const PassDesc& d, const PassDesc* dev, const void* in, void* out,
+                       hipStream_t st) {
+  if (d.tiles <= 0) return hipSuccess;
+  if (d.stw == nullptr) {
+    if constexpr (sizeof(T) == 8)
+      if (d.M > kMaxFastLen64) return launch_len<T, kRtLong>(d, dev, in, out, st);
+    return launch_len<T, kRtShort>(d, dev, in, out, st);
+  }
+#define FM_CALL(TT, M) launch_len<TT, M>(d, dev, in, out, st)
+  switch (d.M) {
+    FM_LEN_CASES(T, FM_CALL)
+    default: return launch_len<T, kRtShort>(d, dev, in, out, st);
+  }
+#undef FM_CALL
+}
+
+// All descriptors of one batched launch share the length class of ds_host[0].
+template <typename T>
+hipError_t launch_pass_batched(int len_class, const PassDesc* ds, const int* prefix, int n,
+                               int total_tiles, int lds_bytes, hipStream_t st) {
+  if (total_tiles <= 0) return hipSuccess;
+#define FM_CALL(TT, M) launch_len_batched<TT, M>(ds, prefix, n, total_tiles, lds_bytes, st)
+  switch (len_class) {
+    FM_LEN_CASES(T, FM_CALL)
+    case kRtLong:
+      if constexpr (sizeof(T) == 8) return launch_len_batched<T, kRtLong>(ds, prefix, n, total_tiles, lds_bytes, st);
+      return hipErrorInvalidValue;
+    default: return launch_len_batched<T, kRtShort>(ds, prefix, n, total_tiles, lds_bytes, st);
+  }
+#undef FM_CALL
+}
+
+template <typename T>
+hipError_t launch_twiddles(void* out, int M, hipStream_t st) {
+  const int n = 4 * M;
+  hipLaunchKernelGGL(twiddle_kernel<T>, dim3((n + 255) / 256), dim3(256), 0, st,
+                     reinterpret_cast<cpx<T>*>(out), M);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_stage_twiddles(void* out, int M, hipStream_t st) {
+  const int n = stage_table_size(M, max_radix((int)sizeof(T)));
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(stage_twiddle_kernel<T>, dim3((n + 255) / 256), dim3(256), 0, st,
+                     reinterpret_cast<cpx<T>*>(out), M);
+  return hipGetLastError();
+}
+
+hipError_t launch_green_sample(double* S, const GreenGen& g, hipStream_t st) {
+  const int64_t total = (int64_t)g.n[0] * g.n[1] * g.n[2];
+  hipLaunchKernelGGL(green_sample_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                     S, g);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_green_final(void* G, const double* S, const int F[3], const int n[3],
+                              const int off[3], double scale, hipStream_t st) {
+  const int64_t total = (int64_t)F[0] * F[1] * F[2];
+  hipLaunchKernelGGL(green_final_kernel<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                     st, reinterpret_cast<T*>(G), S, F[0], F[1], F[2], n[1], n[2], off[0], off[1],
+                     off[2], scale);
+  return hipGetLastError();
+}
+
+template hipError_t launch_pass<float>(const PassDesc&, const PassDesc*, const void*, void*, hipStream_t);
+template hipError_t launch_pass<double>(const PassDesc&, const PassDesc*, const void*, void*, hipStream_t);
+template hipError_t launch_pass_batched<float>(int, const PassDesc*, const int*, int, int, int, hipStream_t);
+template hipError_t launch_pass_batched<double>(int, const PassDesc*, const int*, int, int, int, hipStream_t);
+template hipError_t launch_twiddles<float>(void*, int, hipStream_t);
+template hipError_t launch_twiddles<double>(void*, int, hipStream_t);
+template hipError_t launch_stage_twiddles<float>(void*, int, hipStream_t);
+template hipError_t launch_stage_twiddles<double>(void*, int, hipStream_t);
+template hipError_t launch_green_final<float>(void*, const double*, const int*, const int*, const int*, double, hipStream_t);
+template hipError_t launch_green_final<double>(void*, const double*, const int*, const int*, const int*, double, hipStream_t);
+
+}  // namespace fm

@@ -1,0 +1,99 @@
+// One (precision, length class) instantiation of the pass kernels, compiled once per
+// pair with -DFM_T=<float|double> -DFM_MC=<length, or kRtShort / kRtLong for the
+// runtime-length kernels>.
+#include <cstdlib>
+
+#include "fm_device.h"
+#include "fm_launch.h"
+
+#ifndef FM_T
+#error "FM_T must be defined"
+#endif
+#ifndef FM_MC
+#error "FM_MC must be defined"
+#endif
+
+namespace fm {
+
+template <auto K>
+static hipError_t allow_full_lds() {
+  // let the kernel use the full LDS of a gfx950 workgroup (set once per kernel)
+  static hipError_t once = hipFuncSetAttribute(reinterpret_cast<const void*>(K),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+  return once;
+}
+
+template <int KIND>
+static hipError_t launch_kind(const PassDesc& d, const PassDesc* dev, const void* in, void* out,
+                              hipStream_t st) {
+  if (d.lds_bytes > kSoftLds) {
+    const hipError_t e = allow_full_lds<&pass_kernel<FM_T, FM_MC, KIND>>();
+    if (e != hipSuccess) return e;
+  }
+  // persistent workgroups: as many as can be resident at once (each loops over tiles);
+  // the other kernels take one tile per workgroup
+  if (!pipelined_kernel((int)sizeof(FM_T), FM_MC)) {
+    hipLaunchKernelGGL((pass_kernel<FM_T, FM_MC, KIND>), dim3(d.tiles), dim3(kThreads), d.lds_bytes,
+                       st, dev, in, out);
+    return hipGetLastError();
+  }
+  static int resident[kMaxLds / 256 + 1] = {0};
+  const int slot = d.lds_bytes / 256;
+  if (resident[slot] == 0) {
+    int per_cu = 0, dev_id = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pass_kernel<FM_T, FM_MC, KIND>,
+                                                      kThreads, d.lds_bytes) != hipSuccess ||
+        per_cu < 1)
+      per_cu = 1;
+    if (hipGetDevice(&dev_id) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id) != hipSuccess ||
+        cus < 1)
+      cus = 256;
+    resident[slot] = per_cu * cus;
+  }
+  static const bool persistent = [] {
+    const char* e = std::getenv("FLUXMI_PERSISTENT");
+    return e == nullptr || std::atoi(e) != 0;
+  }();
+  const int grid = (!persistent || d.tiles < resident[slot]) ? d.tiles : resident[slot];
+  hipLaunchKernelGGL((pass_kernel<FM_T, FM_MC, KIND>), dim3(grid), dim3(kThreads), d.lds_bytes, st,
+                     dev, in, out);
+  return hipGetLastError();
+}
+
+template <>
+hipError_t launch_len<FM_T, FM_MC>(const PassDesc& d, const PassDesc* dev, const void* in,
+                                   void* out, hipStream_t st) {
+  switch (d.kind) {
+    case K_C2C_F: return launch_kind<K_C2C_F>(d, dev, in, out, st);
+    case K_C2C_I: return launch_kind<K_C2C_I>(d, dev, in, out, st);
+    case K_R2C: return launch_kind<K_R2C>(d, dev, in, out, st);
+    case K_C2R: return launch_kind<K_C2R>(d, dev, in, out, st);
+    case K_R2R: return launch_kind<K_R2R>(d, dev, in, out, st);
+    case K_F_C2C: return launch_kind<K_F_C2C>(d, dev, in, out, st);
+    case K_F_CURL: return launch_kind<K_F_CURL>(d, dev, in, out, st);
+    case K_F_R2C: return launch_kind<K_F_R2C>(d, dev, in, out, st);
+    case K_F_R2R: return launch_kind<K_F_R2R>(d, dev, in, out, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <>
+hipError_t launch_len_batched<FM_T, FM_MC>(const PassDesc* ds, const int* prefix, int n,
+                                           int total_tiles, int lds_bytes, hipStream_t st) {
+#ifdef FM_NO_BATCHED
+  // the one-launch batched kernels exist in FP64 only; FP32 batches run plan by plan
+  (void)ds; (void)prefix; (void)n; (void)total_tiles; (void)lds_bytes; (void)st;
+  return hipErrorNotSupported;
+#else
+  if (lds_bytes > kSoftLds) {
+    const hipError_t e = allow_full_lds<&pass_kernel_batched<FM_T, FM_MC>>();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((pass_kernel_batched<FM_T, FM_MC>), dim3(total_tiles), dim3(kThreads),
+                     lds_bytes, st, ds, prefix, n);
+  return hipGetLastError();
+#endif
+}
+
+}  // namespace fm

@@ -7,7 +7,32 @@
 namespace fm {
 
 constexpr int kThreads = 256;    // threads per workgroup of every pass kernel
-constexpr int kElems = 16;       // complex values per thread held across a radix stage
+// Kernel length classes: a compile-time FFT length (> 1), or one of the two
+// runtime-length kernels.  FP64 lines longer than kMaxFastLen64 take the long class.
+constexpr int kRtShort = 0;
+constexpr int kRtLong = 1;
+constexpr int kMaxFastLen64 = 2048;
+// Values per thread held across a radix stage for lines of length M (or kernel length
+// class M).  FP64 holds 8 (radices up to 8), so that a stage, its butterfly temporaries
+// and the persistent kernels' prefetch of the next tile stay in VGPRs; FP64 lines
+// longer than kMaxFastLen64 need 16 and run one tile per workgroup without prefetch.
+constexpr int elems_per_thread(int real_bytes, int M) {
+  return (real_bytes == 4 || M == kRtLong || M > kMaxFastLen64) ? 16 : 8;
+}
+constexpr int max_radix(int real_bytes) { return real_bytes == 8 ? 8 : 16; }
+// Persistent kernels with register prefetch: compile-time lengths with 8 FP64 values per
+// thread, every compile-time length in FP32.
+constexpr bool pipelined_kernel(int real_bytes, int MC) {
+  return MC > 1 && (real_bytes == 4 || MC <= kMaxFastLen64);
+}
+// Input values per thread held by the register stage of one tile, per component: complex
+// tiles hold kThreads * elems_per_thread values, real tiles (two lines per FFT) twice
+// that, and the fused Biot-Savart tile (three components) a third per component.  A
+// tile must not hold more input than kThreads times this.
+constexpr int stage_values(int real_bytes, int M, bool in_cplx, int ncl) {
+  return ncl == 3 ? (elems_per_thread(real_bytes, M) + 2) / 3
+                  : (in_cplx ? 1 : 2) * elems_per_thread(real_bytes, M);
+}
 constexpr int kMaxLen = 4096;    // longest FFT
 constexpr int kMaxStages = 16;
 constexpr int kMaxLds = 163840;  // LDS a gfx950 workgroup may allocate
@@ -28,6 +53,22 @@ enum Scatter : int32_t {
   S_REAL2 = 2,  // y1[j] = Re Z[j mod M], y2[j] = Im Z[j mod M]             (inverse R2C)
   S_R2R = 3,    // post-twiddle, real or imaginary part                    (DCT / DST)
 };
+
+// The pass kinds, each compiled as its own kernel (K_ANY: one kernel that reads the
+// kind from the descriptor; used by batched launches).
+enum PassKind : int32_t {
+  K_ANY = 0,
+  K_C2C_F = 1,   // complex forward along a DFT axis (zero padded)
+  K_C2C_I = 2,   // complex inverse (crop / periodic duplicate)
+  K_R2C = 3,     // first DFT axis, forward: two real lines per FFT
+  K_C2R = 4,     // first DFT axis, inverse
+  K_R2R = 5,     // DCT / DST, either direction
+  K_F_C2C = 6,   // fused last axis, complex, Poisson
+  K_F_CURL = 7,  // fused last axis, complex, three components with the spectral curl
+  K_F_R2C = 8,   // fused last axis, the only DFT axis (two real lines per FFT)
+  K_F_R2R = 9,   // fused last axis, all axes real-to-real
+};
+constexpr int kNumKinds = 10;
 
 // Real-to-real transform in the form  y_q = sum_p w_p x_p cs(pi (p+a)(q+b) / nh),
 // evaluated as a length-2nh DFT of a symmetric extension with pre- and post-twiddles.
@@ -62,6 +103,47 @@ struct Fixup {
   int32_t c_dup, c_zero_lo, c_zero_hi, c_last;
 };
 
+// Radix schedule of an FFT length: radix-16 stages first (when rmax allows), then one
+// of 8 / 4 / 2, then 3, 5 and 7.  Shared by the host (table generation) and the device (compile-time
+// stage sequence); returns 0 past the last stage.
+constexpr int radix_at(int M, int s, int rmax) {
+  int m = M;
+  for (int i = 0;; ++i) {
+    int r = 0;
+    if (m > 1) {
+      if (rmax >= 16 && m % 16 == 0) r = 16;
+      else if (m % 8 == 0) r = 8;
+      else if (m % 4 == 0) r = 4;
+      else if (m % 2 == 0) r = 2;
+      else if (m % 3 == 0) r = 3;
+      else if (m % 5 == 0) r = 5;
+      else if (m % 7 == 0) r = 7;
+    }
+    if (i == s || r == 0) return r;
+    m /= r;
+  }
+}
+
+// Lengths with compile-time kernels (other lengths use the runtime-length kernel).
+constexpr int kFastLens[] = {32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 2048, 4096};
+
+// Offset of stage s in the per-length stage twiddle table: stage s holds
+// W_{Ns R}^{k r} for k < Ns (product of the earlier radices), 1 <= r < R.
+constexpr int stage_table_offset(int M, int s, int rmax) {
+  int off = 0, ns = 1;
+  for (int i = 0; i < s; ++i) {
+    const int r = radix_at(M, i, rmax);
+    off += ns * (r - 1);
+    ns *= r;
+  }
+  return off;
+}
+constexpr int stage_table_size(int M, int rmax) {
+  int s = 0;
+  while (radix_at(M, s, rmax) != 0) ++s;
+  return stage_table_offset(M, s, rmax);
+}
+
 struct PassDesc {
   // tile geometry: lines along `line`, B consecutive lines along `b`, index c, comp
   const void* in;
@@ -92,6 +174,14 @@ struct PassDesc {
   Fixup fix;                // last pass only
   int32_t has_fix;
   int32_t lds_bytes;        // dynamic LDS the tile needs
+  // host-precomputed multipliers for division by in_n, out_n, B, spec_n:
+  // n / d = (n * mag) >> 32 for n * d < 2^32
+  uint64_t mag_in, mag_out, mag_B, mag_spec;
+  const void* stw;          // stage twiddle table of a compile-time length (or null)
+  int32_t xcd;              // spread consecutive tiles over one XCD at a time
+  int32_t kind;             // PassKind
+  int32_t raw_off;          // byte offset of the raw input tile in LDS (0: aliases the
+                            // FFT buffer; real-to-real tiles keep it apart)
 };
 
 // Sampling description of the Green's function for the spectrum generation (FP64).

@@ -6,6 +6,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -16,11 +18,15 @@
 #include "fm_pass.h"
 
 namespace fm {
-template <typename T> hipError_t launch_pass(const PassDesc& d, hipStream_t st);
 template <typename T>
-hipError_t launch_pass_batched(const PassDesc* ds, const int* prefix, int n, int total_tiles,
-                               int lds_bytes, hipStream_t st);
+hipError_t launch_pass(const PassDesc& d, const PassDesc* dev, const void* in, void* out,
+                       hipStream_t st);
+template <typename T>
+hipError_t launch_pass_batched(int len_class, const PassDesc* ds, const int* prefix, int n,
+                               int total_tiles, int lds_bytes, hipStream_t st);
 template <typename T> hipError_t launch_twiddles(void* out, int M, hipStream_t st);
+template <typename T> hipError_t launch_stage_twiddles(void* out, int M, hipStream_t st);
+bool is_fast_len(int M);
 
 hipError_t launch_green_sample(double* S, const GreenGen& g, hipStream_t st);
 template <typename T>
@@ -196,7 +202,7 @@ fm::R2R make_r2r(const AxisPlan& a, int kind, bool forward) {
 int radix_plan(int M, fm::PassDesc* d) {
   if (M < 2 || M > fm::kMaxLen) return FM_E_SIZE;
   int m = M, ns = 0;
-  const int rs[] = {8, 4, 2, 3, 5, 7};
+  const int rs[] = {8, 4, 2, 3, 5, 7};  // at most radix 8 (fits both precisions)
   for (int r : rs) {
     while (m % r == 0) {
       if (ns >= fm::kMaxStages) return FM_E_SIZE;
@@ -239,8 +245,10 @@ struct fm_plan_s {
   size_t ws_bytes;
   fm::PassDesc pass[5];
   void* G = nullptr;
+  fm::PassDesc* dpass = nullptr;  // the five descriptors in device memory
   int GF[3];
   std::map<int, void*> tw;
+  std::map<int, void*> stw;
   std::map<int, void*> tw64;
   void* ws_internal = nullptr;
   int device = 0;
@@ -249,32 +257,69 @@ struct fm_plan_s {
 namespace {
 
 size_t round256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// multiplier m = ceil(2^32 / d): n / d == (n * m) >> 32 whenever n * d < 2^32
+uint64_t magic(int d) {
+  const uint64_t dd = (uint64_t)std::max(d, 1);
+  return ((uint64_t(1) << 32) + dd - 1) / dd;
+}
+
+void set_magics(fm::PassDesc* d) {
+  d->mag_in = magic(d->in_n);
+  d->mag_out = magic(d->out_n);
+  d->mag_B = magic(d->B);
+  d->mag_spec = magic(d->spec_n);
+}
+
+int xcd_policy() {
+  static int v = [] {
+    const char* e = std::getenv("FLUXMI_XCD");
+    return e ? std::atoi(e) : 1;
+  }();
+  return v;
+}
 bool pass_in_bounds(const fm::PassDesc& d, int64_t in_size, int64_t out_size, size_t elem);
+int64_t tile_in_span_bytes(const fm::PassDesc& d, size_t elem);
 
 // Largest tile (lines per workgroup) that fits the register budget and, if possible,
 // the preferred LDS size; otherwise the largest that fits the device's LDS.
 int choose_tile(fm::PassDesc* d, size_t elem, int comps, bool fused_r2r, int nb) {
   const int packs = (d->gather == fm::G_CPLX) ? 1 : 2;
+  const bool r2r = d->gather == fm::G_R2R;
   const size_t cplx = 2 * elem;
   const size_t in_elem = d->in_cplx ? cplx : elem;
   for (const int cap : {fm::kSoftLds, fm::kMaxLds}) {
     int best = 0;
-    size_t best_lds = 0;
+    size_t best_lds = 0, best_raw_off = 0;
     for (int B = 1; B <= 64; ++B) {
       const int F = comps * ((B + packs - 1) / packs);
-      if ((int64_t)F * d->M > (int64_t)fm::kThreads * fm::kElems) break;
+      if ((int64_t)F * d->M > (int64_t)fm::kThreads * fm::elems_per_thread((int)elem, d->M)) break;
+      // the register stage must hold the whole input tile (a Hermitian half-spectrum
+      // pair has M + 2 values per FFT line)
+      if ((int64_t)B * d->in_n > (int64_t)fm::kThreads * fm::stage_values((int)elem, d->M, d->in_cplx != 0, comps))
+        break;
       const size_t fft = (size_t)F * (d->M + 1) * cplx;
       const size_t raw = (size_t)comps * B * (d->in_n + 1) * in_elem;
-      size_t lds = std::max(fft, raw);
-      if (fused_r2r) lds = std::max(lds, fft + (size_t)B * (d->spec_n + 1) * elem);
+      size_t lds, raw_off = 0;
+      if (r2r) {
+        // the raw tile (and, fused, the real spectrum after it) sit after the buffer
+        raw_off = round256(fft);
+        size_t extra = raw;
+        if (fused_r2r) extra = std::max(extra, (size_t)B * (d->spec_n + 1) * elem);
+        lds = raw_off + extra;
+      } else {
+        lds = std::max(fft, raw);
+      }
       if (round256(lds) > (size_t)cap) break;
       best = B;
       best_lds = lds;
+      best_raw_off = raw_off;
       if (B >= nb) break;
     }
     if (best > 0) {
       d->B = best;
       d->lds_bytes = (int)round256(best_lds);
+      d->raw_off = (int)best_raw_off;
       return FM_OK;
     }
   }
@@ -342,6 +387,20 @@ int make_tables_and_green(fm_plan_s* p, hipStream_t st) {
     FM_HIP(fm::launch_twiddles<T>(ptr, M, st));
   }
   for (int i = 0; i < 5; ++i) p->pass[i].tw = p->tw[p->pass[i].M];
+  // per-stage tables of the lengths with compile-time kernels
+  for (int i = 0; i < 5; ++i) {
+    const int M = p->pass[i].M;
+    if (!fm::is_fast_len(M)) continue;
+    if (tile_in_span_bytes(p->pass[i], p->elem) >= (int64_t(1) << 32)) continue;
+    if (!p->stw.count(M)) {
+      void* ptr = nullptr;
+      const size_t n = (size_t)std::max(1, fm::stage_table_size(M, fm::max_radix((int)sizeof(T))));
+      if (hipMalloc(&ptr, sizeof(T) * 2 * n) != hipSuccess) return FM_E_NOMEM;
+      p->stw[M] = ptr;
+      FM_HIP(fm::launch_stage_twiddles<T>(ptr, M, st));
+    }
+    p->pass[i].stw = p->stw[M];
+  }
 
   // Green's spectrum: sample (FP64) -> DCT-I along convolution directions -> scale
   const int* o = p->order;  // table axes = (a0, a1, a2), slow -> fast
@@ -377,6 +436,12 @@ int make_tables_and_green(fm_plan_s* p, hipStream_t st) {
   int rc = FM_OK;
   FM_HIP(fm::launch_green_sample(S, g, st));
   int64_t sstr[3] = {(int64_t)Fs[1] * Fs[2], Fs[2], 1};
+  fm::PassDesc gdesc[3];
+  fm::PassDesc* gdev = nullptr;
+  if (hipMalloc(&gdev, sizeof(fm::PassDesc) * 3) != hipSuccess) {
+    (void)hipFree(S);
+    return FM_E_NOMEM;
+  }
   for (int i = 0; i < 3 && rc == FM_OK; ++i) {
     if (!g.unb[i]) continue;
     // DCT-I (REDFT00) of Fs[i] samples, in place along table axis i
@@ -406,6 +471,7 @@ int make_tables_and_green(fm_plan_s* p, hipStream_t st) {
     d.in_n = d.out_n = n;
     if ((rc = choose_tile(&d, sizeof(double), 1, false, d.nb))) break;
     d.tiles = ((d.nb + d.B - 1) / d.B) * d.nc;
+    set_magics(&d);
     if (!pass_in_bounds(d, ns, ns, sizeof(double))) { rc = FM_E_SIZE; break; }
     void* t64 = nullptr;
     auto it = p->tw64.find(d.M);
@@ -417,14 +483,24 @@ int make_tables_and_green(fm_plan_s* p, hipStream_t st) {
       t64 = it->second;
     }
     d.tw = t64;
-    FM_HIP(fm::launch_pass<double>(d, st));
+    d.kind = fm::K_R2R;
+    gdesc[i] = d;
+    FM_HIP(hipMemcpyAsync(gdev + i, &gdesc[i], sizeof(fm::PassDesc), hipMemcpyHostToDevice, st));
+    FM_HIP(fm::launch_pass<double>(gdesc[i], gdev + i, S, S, st));
   }
   if (rc == FM_OK) {
     const int64_t nG = (int64_t)F[0] * F[1] * F[2];
     if (hipMalloc(&p->G, sizeof(T) * nG) != hipSuccess) rc = FM_E_NOMEM;
     else FM_HIP(fm::launch_green_final<T>(p->G, S, F, Fs, off, scale, st));
   }
+  // the five pass descriptors, now complete, go to device memory
+  for (int i = 0; i < 5; ++i) p->pass[i].g.G = p->G;
+  if (rc == FM_OK) {
+    if (hipMalloc(&p->dpass, sizeof(fm::PassDesc) * 5) != hipSuccess) rc = FM_E_NOMEM;
+    else FM_HIP(hipMemcpyAsync(p->dpass, p->pass, sizeof(fm::PassDesc) * 5, hipMemcpyHostToDevice, st));
+  }
   hipError_t e = hipStreamSynchronize(st);
+  (void)hipFree(gdev);
   (void)hipFree(S);
   for (auto& kv : p->tw64) (void)hipFree(kv.second);
   p->tw64.clear();
@@ -437,10 +513,32 @@ int make_tables_and_green(fm_plan_s* p, hipStream_t st) {
 void free_plan(fm_plan_s* p) {
   if (!p) return;
   for (auto& kv : p->tw) (void)hipFree(kv.second);
+  for (auto& kv : p->stw) (void)hipFree(kv.second);
   for (auto& kv : p->tw64) (void)hipFree(kv.second);
   if (p->G) (void)hipFree(p->G);
+  if (p->dpass) (void)hipFree(p->dpass);
   if (p->ws_internal) (void)hipFree(p->ws_internal);
   delete p;
+}
+
+int pass_kind(const fm::PassDesc& d) {
+  if (d.fused) {
+    if (d.gather == fm::G_R2R) return fm::K_F_R2R;
+    if (d.gather == fm::G_REAL2) return fm::K_F_R2C;
+    return d.g.curl ? fm::K_F_CURL : fm::K_F_C2C;
+  }
+  switch (d.gather) {
+    case fm::G_CPLX: return d.sign < 0 ? fm::K_C2C_F : fm::K_C2C_I;
+    case fm::G_REAL2: return fm::K_R2C;
+    case fm::G_HERM2: return fm::K_C2R;
+    default: return fm::K_R2R;
+  }
+}
+
+// Input span of one tile in bytes (the fast kernels address it with 32-bit offsets).
+int64_t tile_in_span_bytes(const fm::PassDesc& d, size_t elem) {
+  const int64_t es = (int64_t)elem * (d.in_cplx ? 2 : 1);
+  return ((int64_t)(d.B - 1) * d.in_s_b + (int64_t)(d.in_n - 1) * d.in_s_line + 1) * es;
 }
 
 // Host-side check of one pass against the buffers and the LDS / register budgets; the
@@ -485,11 +583,19 @@ bool pass_in_bounds(const fm::PassDesc& d, int64_t in_size, int64_t out_size, si
   const int comps = (d.fused && d.g.curl) ? 3 : 1;
   const int packs = (d.gather == fm::G_CPLX) ? 1 : 2;
   const int F = comps * ((d.B + packs - 1) / packs);
-  if ((int64_t)F * M > (int64_t)fm::kThreads * fm::kElems) return false;
+  if ((int64_t)F * M > (int64_t)fm::kThreads * fm::elems_per_thread((int)elem, M)) return false;
+  if ((int64_t)d.B * d.in_n > (int64_t)fm::kThreads * fm::stage_values((int)elem, M, d.in_cplx != 0, comps))
+    return false;
   const size_t fft = (size_t)F * (M + 1) * 2 * elem;
   const size_t raw = (size_t)comps * d.B * (d.in_n + 1) * (d.in_cplx ? 2 : 1) * elem;
   size_t need = std::max(fft, raw);
-  if (d.fused && d.gather == fm::G_R2R) need = std::max(need, fft + (size_t)d.B * (d.spec_n + 1) * elem);
+  if (d.gather == fm::G_R2R) {
+    if ((size_t)d.raw_off < fft) return false;
+    need = d.raw_off + raw;
+    if (d.fused) need = std::max(need, d.raw_off + (size_t)d.B * (d.spec_n + 1) * elem);
+  } else if (d.raw_off != 0) {
+    return false;
+  }
   if (need > (size_t)d.lds_bytes || d.lds_bytes > fm::kMaxLds) return false;
   const int nbt = (d.nb + d.B - 1) / d.B;
   if (d.tiles != nbt * d.nc * (comps == 3 ? 1 : d.ncomp)) return false;
@@ -674,6 +780,19 @@ int build_plan(fm_plan_s* p) {
     d.has_fix = d.fix.b_dup | d.fix.b_zero_lo | d.fix.b_zero_hi | d.fix.c_dup | d.fix.c_zero_lo |
                 d.fix.c_zero_hi;
   }
+  // component strides of the work buffers (elements), fixed by the plan
+  {
+    const int64_t compA = (int64_t)(p->bytesA / (p->elem * (p->cplx1 ? 2 : 1)));
+    const int64_t compB = (int64_t)(p->bytesB / (p->elem * (p->cplx2 ? 2 : 1)));
+    p->pass[0].out_s_comp = compA;
+    p->pass[1].in_s_comp = compA;
+    p->pass[1].out_s_comp = compB;
+    p->pass[2].in_s_comp = compB;
+    p->pass[2].out_s_comp = compB;
+    p->pass[3].in_s_comp = compB;
+    p->pass[3].out_s_comp = compA;
+    p->pass[4].in_s_comp = compA;
+  }
   const int line_axis[5] = {a0, a1, a2, a1, a0};
   for (int i = 0; i < 5; ++i) {
     fm::PassDesc& d = p->pass[i];
@@ -684,7 +803,10 @@ int build_plan(fm_plan_s* p) {
     const int rc2 = choose_tile(&d, p->elem, fused_curl ? 3 : 1, (i == 2) && d.gather == fm::G_R2R, d.nb);
     if (rc2) return rc2;
     d.tiles = ((d.nb + d.B - 1) / d.B) * d.nc * (fused_curl ? 1 : p->ncomp);
+    set_magics(&d);
+    d.xcd = (xcd_policy() && d.tiles >= 64) ? 1 : 0;
   }
+  for (int i = 0; i < 5; ++i) p->pass[i].kind = pass_kind(p->pass[i]);
   const int64_t sizes_in[5] = {p->Vu, p->V1, p->V2, p->V2, p->V1};
   const int64_t sizes_out[5] = {p->V1, p->V2, p->V2, p->V1, p->Vu};
   for (int i = 0; i < 5; ++i)
@@ -693,28 +815,45 @@ int build_plan(fm_plan_s* p) {
 }
 
 
-int launch_all(fm_plan_s* p, fm::PassDesc* ds, hipStream_t st, int first = 0, int last = 4) {
+// Buffers of one solve: pass i reads ins[i] and writes outs[i].  Work buffer A holds
+// the first-axis spectrum (layout L1), B the two-axis spectrum (layout L2).
+void bind_buffers(const fm_plan_s* p, const void* rhs, void* out, char* ws, const void* ins[5],
+                  void* outs[5]) {
+  char* A = ws;
+  char* B = ws + p->ncomp * p->bytesA;
+  ins[0] = rhs; outs[0] = A;
+  ins[1] = A; outs[1] = B;
+  ins[2] = B; outs[2] = B;
+  ins[3] = B; outs[3] = A;
+  ins[4] = A; outs[4] = out;
+}
+
+// FLUXMI_SYNC_DEBUG=1: trace every pass launch on stderr and synchronise after it, so
+// that a failing or stalled launch is named.
+bool sync_debug() {
+  static const bool v = [] {
+    const char* e = std::getenv("FLUXMI_SYNC_DEBUG");
+    return e != nullptr && std::atoi(e) != 0;
+  }();
+  return v;
+}
+
+int launch_all(fm_plan_s* p, const void* const ins[5], void* const outs[5], hipStream_t st,
+               int first = 0, int last = 4) {
   for (int i = first; i <= last; ++i) {
-    hipError_t e = (p->prec == FM_F64) ? fm::launch_pass<double>(ds[i], st)
-                                       : fm::launch_pass<float>(ds[i], st);
+    const fm::PassDesc& d = p->pass[i];
+    if (sync_debug()) {
+      std::fprintf(stderr, "fluxmi: pass %d kind %d M %d prec %s tiles %d B %d lds %d\n", i + 1,
+                   d.kind, d.M, p->prec == FM_F64 ? "f64" : "f32", d.tiles, d.B, d.lds_bytes);
+      std::fflush(stderr);
+    }
+    hipError_t e = (p->prec == FM_F64)
+                       ? fm::launch_pass<double>(d, p->dpass + i, ins[i], outs[i], st)
+                       : fm::launch_pass<float>(d, p->dpass + i, ins[i], outs[i], st);
+    if (e == hipSuccess && sync_debug()) e = hipStreamSynchronize(st);
     if (e != hipSuccess) { g_last_hip = (int)e; return FM_E_HIP; }
   }
   return FM_OK;
-}
-
-void bind_buffers(const fm_plan_s* p, const void* rhs, void* out, char* ws, fm::PassDesc* ds) {
-  char* A = ws;
-  char* B = ws + p->ncomp * p->bytesA;
-  for (int i = 0; i < 5; ++i) ds[i] = p->pass[i];
-  // per-component strides in elements of each buffer
-  const int64_t compA = p->bytesA / (p->elem * (p->cplx1 ? 2 : 1));
-  const int64_t compB = p->bytesB / (p->elem * (p->cplx2 ? 2 : 1));
-  ds[0].in = rhs; ds[0].out = A; ds[0].out_s_comp = compA;
-  ds[1].in = A; ds[1].in_s_comp = compA; ds[1].out = B; ds[1].out_s_comp = compB;
-  ds[2].in = B; ds[2].in_s_comp = compB; ds[2].out = B; ds[2].out_s_comp = compB;
-  ds[2].g.G = p->G;
-  ds[3].in = B; ds[3].in_s_comp = compB; ds[3].out = A; ds[3].out_s_comp = compA;
-  ds[4].in = A; ds[4].in_s_comp = compA; ds[4].out = out;
 }
 
 // Pinned host staging for the batch descriptor tables, one per host thread.  It is
@@ -868,9 +1007,10 @@ int fm_solve(fm_plan p, const void* rhs_dev, void* out_dev, void* workspace_dev,
     }
     ws = reinterpret_cast<char*>(p->ws_internal);
   }
-  fm::PassDesc ds[5];
-  bind_buffers(p, rhs_dev, out_dev, ws, ds);
-  return launch_all(p, ds, st);
+  const void* ins[5];
+  void* outs[5];
+  bind_buffers(p, rhs_dev, out_dev, ws, ins, outs);
+  return launch_all(p, ins, outs, st);
 }
 
 int fm_solve_passes(fm_plan p, const void* rhs_dev, void* out_dev, void* workspace_dev, int first_pass,
@@ -885,9 +1025,10 @@ int fm_solve_passes(fm_plan p, const void* rhs_dev, void* out_dev, void* workspa
     }
     ws = reinterpret_cast<char*>(p->ws_internal);
   }
-  fm::PassDesc ds[5];
-  bind_buffers(p, rhs_dev, out_dev, ws, ds);
-  return launch_all(p, ds, st, first_pass, last_pass);
+  const void* ins[5];
+  void* outs[5];
+  bind_buffers(p, rhs_dev, out_dev, ws, ins, outs);
+  return launch_all(p, ins, outs, st, first_pass, last_pass);
 }
 
 int fm_batched_workspace_bytes(int count, const fm_plan* plans, size_t* bytes) {
@@ -898,8 +1039,9 @@ int fm_batched_workspace_bytes(int count, const fm_plan* plans, size_t* bytes) {
     if (!plans[i]) return FM_E_NULL;
     total += round256(plans[i]->ws_bytes);
   }
-  // descriptor tables: 5 passes x (count descriptors + count+1 prefixes)
-  total += round256(5 * ((size_t)count * sizeof(fm::PassDesc) + (count + 1) * sizeof(int)) + 1024);
+  // descriptor tables: 5 passes x (count descriptors + prefixes), at most 5 * count
+  // length groups each rounded up to 256 bytes twice
+  total += 5 * ((size_t)count * (sizeof(fm::PassDesc) + sizeof(int) + 512) + 512);
   *bytes = total;
   return FM_OK;
 }
@@ -920,18 +1062,66 @@ int fm_solve_batched(int count, const fm_plan* plans, const void* const* rhs_dev
   }
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   char* ws = reinterpret_cast<char*>(workspace_dev);
+  if (prec == FM_F32) {
+    // FP32 batches run plan by plan with the single-solve kernels, each request in its
+    // own slice of the workspace (the one-launch batched kernels exist in FP64 only)
+    size_t o = 0;
+    for (int i = 0; i < count; ++i) {
+      const void* ins[5];
+      void* outs[5];
+      bind_buffers(plans[i], rhs_dev[i], out_dev[i], ws + o, ins, outs);
+      rc = launch_all(plans[i], ins, outs, st);
+      if (rc) return rc;
+      o += round256(plans[i]->ws_bytes);
+    }
+    return FM_OK;
+  }
   // per-request work buffers
   std::vector<fm::PassDesc> all(5 * (size_t)count);
   size_t off = 0;
   for (int i = 0; i < count; ++i) {
-    bind_buffers(plans[i], rhs_dev[i], out_dev[i], ws + off, &all[5 * (size_t)i]);
+    const void* ins[5];
+    void* outs[5];
+    bind_buffers(plans[i], rhs_dev[i], out_dev[i], ws + off, ins, outs);
+    for (int ps = 0; ps < 5; ++ps) {
+      fm::PassDesc& d = all[5 * (size_t)i + ps];
+      d = plans[i]->pass[ps];
+      d.in = ins[ps];
+      d.out = outs[ps];
+    }
     off += round256(plans[i]->ws_bytes);
   }
-  // host staging of the descriptor tables (pinned, reused once the previous copy ended)
-  const size_t desc_bytes = (size_t)count * sizeof(fm::PassDesc);
-  const size_t pref_bytes = round256((count + 1) * sizeof(int));
-  const size_t per_pass = round256(desc_bytes) + pref_bytes;
-  const size_t table_bytes = 5 * per_pass;
+  // Group each pass's descriptors by length class (one launch per class and pass) and
+  // stage the tables in pinned host memory (reused once the previous copy finished).
+  struct Group {
+    int pass, len_class, first, count, tiles, lds;
+    size_t off_desc, off_pref;
+  };
+  std::vector<Group> groups;
+  std::vector<int> order;
+  size_t table_bytes = 0;
+  for (int ps = 0; ps < 5; ++ps) {
+    std::map<int, std::vector<int>> by_class;
+    for (int i = 0; i < count; ++i) {
+      const fm::PassDesc& d = all[5 * (size_t)i + ps];
+      const int rt = (prec == FM_F64 && d.M > fm::kMaxFastLen64) ? fm::kRtLong : fm::kRtShort;
+      by_class[d.stw ? d.M : rt].push_back(i);
+    }
+    for (auto& kv : by_class) {
+      Group g{};
+      g.pass = ps;
+      g.len_class = kv.first;
+      g.first = (int)order.size();
+      g.count = (int)kv.second.size();
+      for (int i : kv.second) order.push_back(i);
+      g.off_desc = table_bytes;
+      table_bytes += round256((size_t)g.count * sizeof(fm::PassDesc));
+      g.off_pref = table_bytes;
+      table_bytes += round256((size_t)(g.count + 1) * sizeof(int));
+      groups.push_back(g);
+    }
+  }
+  if (off + table_bytes > workspace_bytes) return FM_E_ARG;
   if (!g_stage_ptr) g_stage_ptr = new (std::nothrow) BatchStaging();
   if (!g_stage_ptr) return FM_E_NOMEM;
   BatchStaging& sg = *g_stage_ptr;
@@ -949,30 +1139,31 @@ int fm_solve_batched(int count, const fm_plan* plans, const void* const* rhs_dev
   if (!sg.done) FM_HIP(hipEventCreateWithFlags(&sg.done, hipEventDisableTiming));
   char* host = reinterpret_cast<char*>(sg.host);
   char* dev = ws + off;
-  int totals[5], lds[5];
-  for (int ps = 0; ps < 5; ++ps) {
-    fm::PassDesc* hd = reinterpret_cast<fm::PassDesc*>(host + ps * per_pass);
-    int* hp = reinterpret_cast<int*>(host + ps * per_pass + round256(desc_bytes));
+  for (Group& g : groups) {
+    fm::PassDesc* hd = reinterpret_cast<fm::PassDesc*>(host + g.off_desc);
+    int* hp = reinterpret_cast<int*>(host + g.off_pref);
     int acc = 0, mx = 0;
-    for (int i = 0; i < count; ++i) {
-      hd[i] = all[5 * (size_t)i + ps];
-      hp[i] = acc;
-      acc += hd[i].tiles;
-      mx = std::max(mx, hd[i].lds_bytes);
+    for (int j = 0; j < g.count; ++j) {
+      const int i = order[g.first + j];
+      hd[j] = all[5 * (size_t)i + g.pass];
+      hd[j].xcd = 0;
+      hp[j] = acc;
+      acc += hd[j].tiles;
+      mx = std::max(mx, hd[j].lds_bytes);
     }
-    hp[count] = acc;
-    totals[ps] = acc;
-    lds[ps] = mx;
+    hp[g.count] = acc;
+    g.tiles = acc;
+    g.lds = mx;
   }
   FM_HIP(hipMemcpyAsync(dev, host, table_bytes, hipMemcpyHostToDevice, st));
   FM_HIP(hipEventRecord(sg.done, st));
   sg.pending = true;
-  for (int ps = 0; ps < 5; ++ps) {
-    const fm::PassDesc* dd = reinterpret_cast<const fm::PassDesc*>(dev + ps * per_pass);
-    const int* dp = reinterpret_cast<const int*>(dev + ps * per_pass + round256(desc_bytes));
+  for (const Group& g : groups) {
+    const fm::PassDesc* dd = reinterpret_cast<const fm::PassDesc*>(dev + g.off_desc);
+    const int* dp = reinterpret_cast<const int*>(dev + g.off_pref);
     hipError_t e = (prec == FM_F64)
-                       ? fm::launch_pass_batched<double>(dd, dp, count, totals[ps], lds[ps], st)
-                       : fm::launch_pass_batched<float>(dd, dp, count, totals[ps], lds[ps], st);
+                       ? fm::launch_pass_batched<double>(g.len_class, dd, dp, g.count, g.tiles, g.lds, st)
+                       : fm::launch_pass_batched<float>(g.len_class, dd, dp, g.count, g.tiles, g.lds, st);
     if (e != hipSuccess) { g_last_hip = (int)e; return FM_E_HIP; }
   }
   return FM_OK;

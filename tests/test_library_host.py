@@ -75,3 +75,20 @@ def test_workspace_and_padding_sizes():
     assert info["fft_len"] == [1024] * 3
     assert info["spec_len"] == [513, 1024, 1024]
     assert info["green_dims"] == [513, 513, 513]
+
+
+@pytest.mark.parametrize("prec,values", [(F.F64, 256 * 8), (F.F32, 256 * 16)])
+def test_tile_input_fits_register_stage(prec, values):
+    # The inverse real-to-complex pass reads two Hermitian half-spectra (M/2 + 1 complex
+    # values each) per FFT line: its tile must still fit the register stage of the
+    # persistent kernels, or the tail of the tile is never loaded.
+    n, h = [128, 128, 256], [1 / 128] * 3
+    info = F.plan_inspect(n, h, [[2, 2], [0, 1], [3, 3]], 1, F.CHAT2, prec)
+    assert info["order"] == [1, 0, 2]
+    assert info["lines_per_tile"][3] * 65 <= values
+    # every length a periodic axis may take, both layouts: the planner's own validator
+    # rejects a tile that overflows the stage, so planning must succeed
+    for m in (4, 8, 16, 32, 64, 96, 128, 256, 512, 1024, 2048, 4096):
+        for layout in (0, 1):
+            F.plan_inspect([m, 8, 6], [0.1] * 3, [[2, 2], [0, 1], [3, 3]], layout, F.CHAT2, prec)
+            F.plan_inspect([6, m, 8], [0.1] * 3, [[3, 3], [2, 2], [3, 3]], layout, F.CHAT2, prec)
