@@ -210,6 +210,38 @@ constexpr bool in_cplx_of(int k) {
 }
 constexpr bool fused_of(int k) { return k >= K_F_C2C; }
 
+// A table pointer of the descriptor as a global-memory pointer.  Descriptor pointers
+// are generic; a generic load is a FLAT instruction, which counts against both the
+// vector-memory and the LDS counters, so that every later LDS wait would also wait for
+// it.  Global pointers give plain global loads.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* gptr(const void* p) {
+  return (const __attribute__((address_space(1))) T*)(p);
+}
+
+// Per-element loops over a tile take kChunk elements per thread at a time, so that
+// their LDS reads are issued together.
+constexpr int kChunk = 1;
+
+// for e in [0, total) spread over the workgroup: v = ld(e) for a chunk of elements,
+// then st(e, v) for the same chunk (all reads of a chunk precede its writes).
+template <typename V, class Ld, class St>
+__device__ __forceinline__ void chunked(int total, const Ld& ld, const St& st) {
+  for (int e0 = threadIdx.x; e0 < total; e0 += kChunk * kThreads) {
+    V v[kChunk];
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u) {
+      const int e = e0 + u * kThreads;
+      if (e < total) v[u] = ld(e);
+    }
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u) {
+      const int e = e0 + u * kThreads;
+      if (e < total) st(e, v[u]);
+    }
+  }
+}
+
 template <typename T>
 struct Prec {
   static constexpr int RMAX = max_radix((int)sizeof(T));
@@ -349,9 +381,9 @@ __device__ __forceinline__ void fft_stage_dispatch(int R, cpx<T>* buf, int ls, i
 // Full FFT of F lines; result in buf in natural order.  MC = compile-time length or 0.
 template <typename T, int MC, int S, class Load>
 __device__ __forceinline__ void fft_lines(cpx<T>* buf, int ls, int F, const PassDesc& d,
-                                          Load& load0) {
+                                          const cpx<T>* stw, Load& load0) {
   if constexpr (MC > 1) {
-    stages_ct<T, MC, S, 0, 1>(buf, ls, F, reinterpret_cast<const cpx<T>*>(d.stw), load0);
+    stages_ct<T, MC, S, 0, 1>(buf, ls, F, stw, load0);
   } else {
     constexpr int EL = elems_per_thread((int)sizeof(T), MC);
     const cpx<T>* tw = reinterpret_cast<const cpx<T>*>(d.tw);
@@ -365,6 +397,14 @@ __device__ __forceinline__ void fft_lines(cpx<T>* buf, int ls, int F, const Pass
     }
   }
 }
+
+// Twiddle tables seen by a tile: in LDS for persistent kernels (copied once per
+// workgroup), else in global memory.
+template <typename T>
+struct Tabs {
+  const cpx<T>* stw;  // stage twiddles of the compile-time length
+  const cpx<T>* tw;   // 4M table (persistent real-to-real kernels: its first 2M entries)
+};
 
 // ---------------------------------------------------------------------------------
 // Gathers: value of slot m of FFT line f, from the raw tile in LDS.
@@ -410,40 +450,41 @@ struct GatherHerm2 {  // two Hermitian half-spectra -> one full spectrum
   }
 };
 
-__device__ __forceinline__ int r2r_weight(const R2R& r, int p) {
-  return p == r.plo ? r.wlo : (p == r.phi ? r.whi : 2);
-}
-
 template <typename T>
 struct GatherR2R {  // symmetric extension of two real lines, with pre-twiddle
   const T* raw;
   int rs, in_n, nl;
   R2R r;
   const cpx<T>* tw;  // 4M table
+  // Branch-free: the mirrored source index and its weight are selected per lane, the
+  // index is clamped into the line, and a sample outside the data gets weight 0.
   __device__ cpx<T> operator()(int f, int m) const {
-    const int M = 2 * r.nh;
+    const int nh = r.nh, M = 2 * nh;
     const int l = 2 * f;
     const T eps = r.b2 ? T(-1) : T(1);          // wrap factor of a full period
     const T sigma = r.sin ? -eps : eps;          // sign of the mirrored sample
-    T re = T(0), im = T(0);
-    auto add = [&](int p, T coef) {
-      if (p < r.plo || p > r.phi) return;
-      const int j = r.in_rev ? r.in_base - p : p - r.in_base;
-      if (j < 0 || j >= in_n) return;
-      const T c = coef * T(r2r_weight(r, p)) * T(0.5);
-      re += c * raw[l * rs + j];
-      if (l + 1 < nl) im += c * raw[(l + 1) * rs + j];
-    };
-    if (r.a2 == 0) {
-      if (m == 0) add(0, T(1) + sigma * eps);
-      else if (m == r.nh) add(r.nh, T(1) + sigma);
-      else if (m < r.nh) add(m, T(1));
-      else add(M - m, sigma);
-    } else {
-      if (m < r.nh) add(m, T(1));
-      else add(M - 1 - m, sigma);
+    int p;
+    T coef;
+    if (r.a2 == 0) {  // whole-sample symmetry: p and M - p share a sample
+      const bool hi = m > nh;
+      p = hi ? M - m : m;
+      coef = hi ? sigma : T(1);
+      coef = (m == 0) ? T(1) + sigma * eps : coef;
+      coef = (m == nh) ? T(1) + sigma : coef;
+    } else {          // half-sample symmetry: p and M - 1 - p
+      const bool hi = m >= nh;
+      p = hi ? M - 1 - m : m;
+      coef = hi ? sigma : T(1);
     }
-    cpx<T> z = {re, im};
+    const int j = r.in_rev ? r.in_base - p : p - r.in_base;
+    const bool ok = p >= r.plo && p <= r.phi && j >= 0 && j < in_n;
+    const int jc = ok ? j : 0;
+    const T w = T(p == r.plo ? r.wlo : (p == r.phi ? r.whi : 2));
+    const T c = ok ? coef * w * T(0.5) : T(0);
+    const bool two = l + 1 < nl;
+    const T a = raw[l * rs + jc];
+    const T b = raw[(two ? l + 1 : l) * rs + jc];
+    cpx<T> z = {c * a, two ? c * b : T(0)};
     if (r.b2) z = cmul(z, tw[2 * m]);  // exp(-i pi m b / nh), b = 1/2
     return z;
   }
@@ -454,9 +495,24 @@ struct GatherR2R {  // symmetric extension of two real lines, with pre-twiddle
 template <typename T, int MC>
 __device__ __forceinline__ void extend_r2r(cpx<T>* buf, int ls, int F, int M, const GatherR2R<T>& g) {
   const int total = F * M;
-  for (int e = threadIdx.x; e < total; e += kThreads) {
-    const int f = e / M, m = e - f * M;
-    buf[f * ls + m] = g(f, m);
+  for (int e0 = threadIdx.x; e0 < total; e0 += kChunk * kThreads) {
+    cpx<T> z[kChunk];
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u) {
+      const int e = e0 + u * kThreads;
+      if (e < total) {
+        const int f = e / M, m = e - f * M;
+        z[u] = g(f, m);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u) {
+      const int e = e0 + u * kThreads;
+      if (e < total) {
+        const int f = e / M, m = e - f * M;
+        buf[f * ls + m] = z[u];
+      }
+    }
   }
   __syncthreads();
 }
@@ -468,70 +524,24 @@ template <typename T>
 __device__ __forceinline__ T scatter_r2r(const cpx<T>* buf, int ls, const R2R& r,
                                          const cpx<T>* tw, int l, int j) {
   const int q = r.out_rev ? r.out_base - j : j + r.out_base;
-  if (q < r.qlo || q > r.qhi) return T(0);
-  cpx<T> Y = buf[(l >> 1) * ls + q];
-  if (r.a2) Y = cmul(Y, tw[2 * q + r.b2]);  // exp(-i pi a (q + b) / nh), a = 1/2
-  if (!r.sin) return (l & 1) ? Y.y : Y.x;
-  return (l & 1) ? Y.x : -Y.y;
+  const bool ok = q >= r.qlo && q <= r.qhi;   // outside: the coefficient is 0
+  const int qc = ok ? q : r.qlo;
+  cpx<T> Y = buf[(l >> 1) * ls + qc];
+  if (r.a2) Y = cmul(Y, tw[2 * qc + r.b2]);  // exp(-i pi a (q + b) / nh), a = 1/2
+  const T v = r.sin ? ((l & 1) ? Y.x : -Y.y) : ((l & 1) ? Y.y : Y.x);
+  return ok ? v : T(0);
 }
 
 // ---------------------------------------------------------------------------------
-// Coalesced tile load / store.  Element e of the tile maps to (line l, index i):
+// Coalesced tile store.  Element e of the tile maps to (line l, index i):
 // line-contiguous data walk along the line (l = e / n), otherwise across the B lines
-// of the tile (i = e / B); divisions use host-computed multipliers.  Loads are issued
-// kUnroll at a time before their LDS writes so that several are in flight.
+// of the tile (i = e / B); divisions use host-computed multipliers.
 // ---------------------------------------------------------------------------------
-constexpr int kUnroll = 4;
-
-template <typename E>
-__device__ __forceinline__ void load_tile(const E* __restrict__ in, int64_t s_line, int64_t s_b,
-                                          int nl, int n, uint64_t mag_n, int B, uint64_t mag_B,
-                                          E* raw, int rs) {
-  if (s_line == 1) {
-    const int total = nl * n;
-    for (int base = threadIdx.x; base < total; base += kUnroll * kThreads) {
-      E v[kUnroll];
-      int dst[kUnroll];
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const int e = base + u * kThreads;
-        dst[u] = -1;
-        if (e < total) {
-          const int l = (int)fdiv(e, mag_n), i = e - l * n;
-          v[u] = in[l * s_b + i];
-          dst[u] = l * rs + i;
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u)
-        if (dst[u] >= 0) raw[dst[u]] = v[u];
-    }
-  } else {
-    const int total = B * n;
-    for (int base = threadIdx.x; base < total; base += kUnroll * kThreads) {
-      E v[kUnroll];
-      int dst[kUnroll];
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const int e = base + u * kThreads;
-        dst[u] = -1;
-        if (e < total) {
-          const int i = (int)fdiv(e, mag_B), l = e - i * B;
-          if (l < nl) {
-            v[u] = in[l * s_b + (int64_t)i * s_line];
-            dst[u] = l * rs + i;
-          }
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u)
-        if (dst[u] >= 0) raw[dst[u]] = v[u];
-    }
-  }
-}
-
 // Store with the output conventions of the batch axes (last pass): `out` points at
 // (c, b0); writes 0 on odd faces and duplicates index 0 to index last when asked.
+// Elements are taken kChunk at a time: all their LDS reads (inside `val`) are issued
+// before the first global store, so that one LDS round trip serves the whole chunk.
+
 template <bool FIX, typename E, class Val>
 __device__ __forceinline__ void store_tile(E* __restrict__ out, int64_t s_line, int64_t s_b,
                                            int64_t s_c, int nl, int n, uint64_t mag_n, int B,
@@ -544,30 +554,46 @@ __device__ __forceinline__ void store_tile(E* __restrict__ out, int64_t s_line, 
   }
   const bool lc = (s_line == 1);
   const int total = lc ? nl * n : B * n;
-  for (int e = threadIdx.x; e < total; e += kThreads) {
-    int l, j;
-    if (lc) {
-      l = (int)fdiv(e, mag_n);
-      j = e - l * n;
-    } else {
-      j = (int)fdiv(e, mag_B);
-      l = e - j * B;
-      if (l >= nl) continue;
-    }
-    E v = val(l, j);
-    const int64_t o = l * s_b + (int64_t)j * s_line;
-    if (FIX) {
-      const int b = b0 + l;
-      if (czero || (fx.b_zero_lo && b == 0) || (fx.b_zero_hi && b == fx.b_last)) v = E{};
-      out[o] = v;
-      const bool bdup = fx.b_dup && b == 0;
-      if (bdup) out[o + (int64_t)fx.b_last * s_b] = v;
-      if (cdup) {
-        out[o + (int64_t)fx.c_last * s_c] = v;
-        if (bdup) out[o + (int64_t)fx.b_last * s_b + (int64_t)fx.c_last * s_c] = v;
+  for (int e0 = threadIdx.x; e0 < total; e0 += kChunk * kThreads) {
+    E v[kChunk];
+    int lj[kChunk], jj[kChunk];
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u) {
+      const int e = e0 + u * kThreads;
+      int l = -1, j = 0;
+      if (e < total) {
+        if (lc) {
+          l = (int)fdiv(e, mag_n);
+          j = e - l * n;
+        } else {
+          j = (int)fdiv(e, mag_B);
+          l = e - j * B;
+          if (l >= nl) l = -1;
+        }
       }
-    } else {
-      out[o] = v;
+      lj[u] = l;
+      jj[u] = j;
+      if (l >= 0) v[u] = val(l, j);
+    }
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u) {
+      const int l = lj[u];
+      if (l < 0) continue;
+      const int64_t o = l * s_b + (int64_t)jj[u] * s_line;
+      if (FIX) {
+        const int b = b0 + l;
+        E w = v[u];
+        if (czero || (fx.b_zero_lo && b == 0) || (fx.b_zero_hi && b == fx.b_last)) w = E{};
+        out[o] = w;
+        const bool bdup = fx.b_dup && b == 0;
+        if (bdup) out[o + (int64_t)fx.b_last * s_b] = w;
+        if (cdup) {
+          out[o + (int64_t)fx.c_last * s_c] = w;
+          if (bdup) out[o + (int64_t)fx.b_last * s_b + (int64_t)fx.c_last * s_c] = w;
+        }
+      } else {
+        out[o] = v[u];
+      }
     }
   }
 }
@@ -613,12 +639,13 @@ __device__ __forceinline__ void store_real(const PassDesc& d, void* out, const T
 }
 
 template <typename T, int MC, int KIND>
-__device__ void plain_compute(const PassDesc& d, void* out, const TileIdx& ti, char* smem) {
+__device__ void plain_compute(const PassDesc& d, void* out, const TileIdx& ti, char* smem,
+                              const Tabs<T>& tb) {
   const int gather = KIND == K_ANY ? d.gather : gather_of(KIND);
   const int scatter = KIND == K_ANY ? d.scatter : scatter_of(KIND);
   const int sign = KIND == K_ANY ? d.sign : (KIND == K_C2C_I || KIND == K_C2R ? +1 : -1);
   const int nl = ti.nl;
-  const cpx<T>* tw = reinterpret_cast<const cpx<T>*>(d.tw);
+  const cpx<T>* tw = tb.tw;
   const int M = MC > 1 ? MC : d.M;
   const int ls = M + 1;
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem);
@@ -629,19 +656,19 @@ __device__ void plain_compute(const PassDesc& d, void* out, const TileIdx& ti, c
   const int F = (gather == G_CPLX) ? nl : (nl + 1) / 2;
   if (gather == G_CPLX) {
     GatherCplx<T> g{reinterpret_cast<const cpx<T>*>(smem), rs, d.n_data};
-    if (sign < 0) fft_lines<T, MC, -1>(buf, ls, F, d, g);
-    else fft_lines<T, MC, +1>(buf, ls, F, d, g);
+    if (sign < 0) fft_lines<T, MC, -1>(buf, ls, F, d, tb.stw, g);
+    else fft_lines<T, MC, +1>(buf, ls, F, d, tb.stw, g);
   } else if (gather == G_REAL2) {
     GatherReal2<T> g{reinterpret_cast<const T*>(smem), rs, d.n_data, nl};
-    fft_lines<T, MC, -1>(buf, ls, F, d, g);
+    fft_lines<T, MC, -1>(buf, ls, F, d, tb.stw, g);
   } else if (gather == G_HERM2) {
     GatherHerm2<T> g{reinterpret_cast<const cpx<T>*>(smem), rs, M, nl};
-    fft_lines<T, MC, +1>(buf, ls, F, d, g);
+    fft_lines<T, MC, +1>(buf, ls, F, d, tb.stw, g);
   } else {
     GatherR2R<T> g{reinterpret_cast<const T*>(smem + d.raw_off), rs, d.in_n, nl, d.r2r, tw};
     extend_r2r<T, MC>(buf, ls, F, M, g);
     auto lds = [buf, ls](int line, int idx) { return buf[line * ls + idx]; };
-    fft_lines<T, MC, -1>(buf, ls, F, d, lds);
+    fft_lines<T, MC, -1>(buf, ls, F, d, tb.stw, lds);
   }
 
   // 3) write the lines into the output layout
@@ -676,18 +703,20 @@ __device__ void plain_compute(const PassDesc& d, void* out, const TileIdx& ti, c
 // Fused pass 3 on one tile: forward FFT, spectral multiply, inverse FFT.
 // ---------------------------------------------------------------------------------
 template <typename T, int MC, int KIND>
-__device__ void fused_compute(const PassDesc& d, void* out, const TileIdx& ti, char* smem) {
+__device__ void fused_compute(const PassDesc& d, void* out, const TileIdx& ti, char* smem,
+                              const Tabs<T>& tb) {
   const int gather = KIND == K_ANY ? d.gather : gather_of(KIND);
   const bool curl = KIND == K_ANY ? (d.g.curl != 0) : (KIND == K_F_CURL);
   const int nl = ti.nl, b0 = ti.b0, c = ti.c, comp = ti.comp;  // curl: comp = 0
-  const cpx<T>* tw = reinterpret_cast<const cpx<T>*>(d.tw);
+  const cpx<T>* tw = tb.tw;
   const int M = MC > 1 ? MC : d.M;
   const int ls = M + 1;
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem);
   const int rs = d.in_n + 1;
   const int ncl = curl ? 3 : 1;   // components held by the tile
-  const T* G = reinterpret_cast<const T*>(d.g.G);
-  const int fc = fold_index(c, d.g.fold_c);
+  // the tile's Green rows, staged in LDS with the tile: row l holds F_line values
+  const T* gl = reinterpret_cast<const T*>(smem + d.g_off);
+  const int FL = d.g.F_line;
   const Fixup nofix{};
 
   if (gather == G_R2R) {
@@ -697,23 +726,27 @@ __device__ void fused_compute(const PassDesc& d, void* out, const TileIdx& ti, c
     {
       GatherR2R<T> g{reinterpret_cast<const T*>(smem + d.raw_off), rs, d.in_n, nl, d.r2r, tw};
       extend_r2r<T, MC>(buf, ls, F, M, g);
-      fft_lines<T, MC, -1>(buf, ls, F, d, lds);
+      fft_lines<T, MC, -1>(buf, ls, F, d, tb.stw, lds);
     }
     // spectrum (real) into its own LDS region (where the raw tile was), times the
     // Green's spectrum
     const int ss = d.spec_n + 1;
     T* spec = reinterpret_cast<T*>(smem + d.raw_off);
-    for (int e = threadIdx.x; e < nl * d.spec_n; e += kThreads) {
-      const int l = (int)fdiv(e, d.mag_spec), j = e - l * d.spec_n;
-      const T g = G[((int64_t)fc * d.g.F_b + fold_index(b0 + l, d.g.fold_b)) * d.g.F_line +
-                    fold_index(j, d.g.fold_line)];
-      spec[l * ss + j] = g * scatter_r2r<T>(buf, ls, d.r2r, tw, l, j);
-    }
+    chunked<T>(
+        nl * d.spec_n,
+        [&](int e) {
+          const int l = (int)fdiv(e, d.mag_spec), j = e - l * d.spec_n;
+          return gl[l * FL + fold_index(j, d.g.fold_line)] * scatter_r2r<T>(buf, ls, d.r2r, tw, l, j);
+        },
+        [&](int e, T v) {
+          const int l = (int)fdiv(e, d.mag_spec), j = e - l * d.spec_n;
+          spec[l * ss + j] = v;
+        });
     __syncthreads();
     {
       GatherR2R<T> g{spec, ss, d.spec_n, nl, d.r2r2, tw};
       extend_r2r<T, MC>(buf, ls, F, M, g);
-      fft_lines<T, MC, -1>(buf, ls, F, d, lds);
+      fft_lines<T, MC, -1>(buf, ls, F, d, tb.stw, lds);
     }
     const int64_t out_off = comp * d.out_s_comp + c * d.out_s_c + b0 * d.out_s_b;
     auto val = [&](int l, int j) { return scatter_r2r<T>(buf, ls, d.r2r2, tw, l, j); };
@@ -726,29 +759,40 @@ __device__ void fused_compute(const PassDesc& d, void* out, const TileIdx& ti, c
     // ---- only DFT axis of the problem: two real lines per FFT
     const int F = (nl + 1) / 2;
     GatherReal2<T> g{reinterpret_cast<const T*>(smem), rs, d.n_data, nl};
-    fft_lines<T, MC, -1>(buf, ls, F, d, g);
+    fft_lines<T, MC, -1>(buf, ls, F, d, tb.stw, g);
     // The two packed lines have their own Green rows: split Z into the two Hermitian
     // spectra X1 = (Z_k + conj Z_{M-k})/2, X2 = (Z_k - conj Z_{M-k})/(2i), scale each
     // by its (real, even) row, and pack again as Y1 + i Y2.  One thread owns the pair
     // (k, M-k).
     const int H = M / 2 + 1;
-    for (int e = threadIdx.x; e < F * H; e += kThreads) {
-      const int f = e / H, k = e - f * H;
-      const int kk = fold_index(k, d.g.fold_line);
-      const int l0 = 2 * f, l1 = min(2 * f + 1, nl - 1);
-      const T g0 = G[((int64_t)fc * d.g.F_b + fold_index(b0 + l0, d.g.fold_b)) * d.g.F_line + kk];
-      const T g1 = G[((int64_t)fc * d.g.F_b + fold_index(b0 + l1, d.g.fold_b)) * d.g.F_line + kk];
-      const int km = (k == 0) ? 0 : M - k;
-      const cpx<T> zk = buf[f * ls + k], zm = buf[f * ls + km];
-      const cpx<T> x1 = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
-      const cpx<T> x2 = {T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x)};
-      // Z'_k = g0 X1 + i g1 X2 ;  Z'_{M-k} = g0 conj(X1) + i g1 conj(X2)
-      buf[f * ls + k] = {g0 * x1.x - g1 * x2.y, g0 * x1.y + g1 * x2.x};
-      if (km != k) buf[f * ls + km] = {g0 * x1.x + g1 * x2.y, -g0 * x1.y + g1 * x2.x};
-    }
+    struct Pair {
+      cpx<T> a, b;
+    };
+    chunked<Pair>(
+        F * H,
+        [&](int e) {
+          const int f = e / H, k = e - f * H;
+          const int kk = fold_index(k, d.g.fold_line);
+          const int l0 = 2 * f, l1 = min(2 * f + 1, nl - 1);
+          const T g0 = gl[l0 * FL + kk];
+          const T g1 = gl[l1 * FL + kk];
+          const int km = (k == 0) ? 0 : M - k;
+          const cpx<T> zk = buf[f * ls + k], zm = buf[f * ls + km];
+          const cpx<T> x1 = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
+          const cpx<T> x2 = {T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x)};
+          // Z'_k = g0 X1 + i g1 X2 ;  Z'_{M-k} = g0 conj(X1) + i g1 conj(X2)
+          return Pair{{g0 * x1.x - g1 * x2.y, g0 * x1.y + g1 * x2.x},
+                      {g0 * x1.x + g1 * x2.y, -g0 * x1.y + g1 * x2.x}};
+        },
+        [&](int e, const Pair& v) {
+          const int f = e / H, k = e - f * H;
+          const int km = (k == 0) ? 0 : M - k;
+          buf[f * ls + k] = v.a;
+          if (km != k) buf[f * ls + km] = v.b;
+        });
     __syncthreads();
     auto lds = [buf, ls](int line, int idx) { return buf[line * ls + idx]; };
-    fft_lines<T, MC, +1>(buf, ls, F, d, lds);
+    fft_lines<T, MC, +1>(buf, ls, F, d, tb.stw, lds);
     const int64_t out_off = comp * d.out_s_comp + c * d.out_s_c + b0 * d.out_s_b;
     auto val = [&](int l, int j) {
       const cpx<T> z = buf[(l >> 1) * ls + (j < M ? j : j - M)];
@@ -763,46 +807,57 @@ __device__ void fused_compute(const PassDesc& d, void* out, const TileIdx& ti, c
   const int F = ncl * nl;
   {
     GatherCplx<T> g{reinterpret_cast<const cpx<T>*>(smem), rs, d.n_data};
-    fft_lines<T, MC, -1>(buf, ls, F, d, g);
+    fft_lines<T, MC, -1>(buf, ls, F, d, tb.stw, g);
   }
   if (!curl) {
-    for (int e = threadIdx.x; e < nl * M; e += kThreads) {
-      const int l = e / M, k = e - l * M;
-      const T g = G[((int64_t)fc * d.g.F_b + fold_index(b0 + l, d.g.fold_b)) * d.g.F_line +
-                    fold_index(k, d.g.fold_line)];
-      cpx<T> z = buf[l * ls + k];
-      z.x *= g;
-      z.y *= g;
-      buf[l * ls + k] = z;
-    }
+    chunked<cpx<T>>(
+        nl * M,
+        [&](int e) {
+          const int l = e / M, k = e - l * M;
+          const T g = gl[l * FL + fold_index(k, d.g.fold_line)];
+          const cpx<T> z = buf[l * ls + k];
+          return cpx<T>{z.x * g, z.y * g};
+        },
+        [&](int e, const cpx<T>& v) {
+          const int l = e / M, k = e - l * M;
+          buf[l * ls + k] = v;
+        });
   } else {
     const T wc = signed_wave<T>(c, d.g.M_c, T(d.g.dw_c));
     const T dwl = T(d.g.dw_line), dwb = T(d.g.dw_b);
-    for (int e = threadIdx.x; e < nl * M; e += kThreads) {
-      const int l = e / M, k = e - l * M;
-      const T g = G[((int64_t)fc * d.g.F_b + fold_index(b0 + l, d.g.fold_b)) * d.g.F_line +
-                    fold_index(k, d.g.fold_line)];
-      const T wl = signed_wave<T>(k, d.g.M_line, dwl);
-      const T wb = signed_wave<T>(b0 + l, d.g.M_b, dwb);
-      const T wx = d.g.axis_line == 0 ? wl : (d.g.axis_b == 0 ? wb : wc);
-      const T wy = d.g.axis_line == 1 ? wl : (d.g.axis_b == 1 ? wb : wc);
-      const T wz = d.g.axis_line == 2 ? wl : (d.g.axis_b == 2 ? wb : wc);
-      const cpx<T> fx = buf[(0 * nl + l) * ls + k];
-      const cpx<T> fy = buf[(1 * nl + l) * ls + k];
-      const cpx<T> fz = buf[(2 * nl + l) * ls + k];
-      // u_hat = G * i (w x f_hat)
-      const cpx<T> cx = {wy * fz.x - wz * fy.x, wy * fz.y - wz * fy.y};
-      const cpx<T> cy = {wz * fx.x - wx * fz.x, wz * fx.y - wx * fz.y};
-      const cpx<T> cz = {wx * fy.x - wy * fx.x, wx * fy.y - wy * fx.y};
-      buf[(0 * nl + l) * ls + k] = {-g * cx.y, g * cx.x};
-      buf[(1 * nl + l) * ls + k] = {-g * cy.y, g * cy.x};
-      buf[(2 * nl + l) * ls + k] = {-g * cz.y, g * cz.x};
-    }
+    struct Tri {
+      cpx<T> x, y, z;
+    };
+    chunked<Tri>(
+        nl * M,
+        [&](int e) {
+          const int l = e / M, k = e - l * M;
+          const T g = gl[l * FL + fold_index(k, d.g.fold_line)];
+          const T wl = signed_wave<T>(k, d.g.M_line, dwl);
+          const T wb = signed_wave<T>(b0 + l, d.g.M_b, dwb);
+          const T wx = d.g.axis_line == 0 ? wl : (d.g.axis_b == 0 ? wb : wc);
+          const T wy = d.g.axis_line == 1 ? wl : (d.g.axis_b == 1 ? wb : wc);
+          const T wz = d.g.axis_line == 2 ? wl : (d.g.axis_b == 2 ? wb : wc);
+          const cpx<T> fx = buf[(0 * nl + l) * ls + k];
+          const cpx<T> fy = buf[(1 * nl + l) * ls + k];
+          const cpx<T> fz = buf[(2 * nl + l) * ls + k];
+          // u_hat = G * i (w x f_hat)
+          const cpx<T> cx = {wy * fz.x - wz * fy.x, wy * fz.y - wz * fy.y};
+          const cpx<T> cy = {wz * fx.x - wx * fz.x, wz * fx.y - wx * fz.y};
+          const cpx<T> cz = {wx * fy.x - wy * fx.x, wx * fy.y - wy * fx.y};
+          return Tri{{-g * cx.y, g * cx.x}, {-g * cy.y, g * cy.x}, {-g * cz.y, g * cz.x}};
+        },
+        [&](int e, const Tri& v) {
+          const int l = e / M, k = e - l * M;
+          buf[(0 * nl + l) * ls + k] = v.x;
+          buf[(1 * nl + l) * ls + k] = v.y;
+          buf[(2 * nl + l) * ls + k] = v.z;
+        });
   }
   __syncthreads();
   {
     auto lds = [buf, ls](int line, int idx) { return buf[line * ls + idx]; };
-    fft_lines<T, MC, +1>(buf, ls, F, d, lds);
+    fft_lines<T, MC, +1>(buf, ls, F, d, tb.stw, lds);
   }
   for (int q = 0; q < ncl; ++q) {
     const int cc = curl ? q : comp;
@@ -922,16 +977,67 @@ __device__ __forceinline__ void commit(const Stage& v, const PassDesc& d, const 
   }
 }
 
+// The Green rows of a fused tile (nl rows of g.F_line values) travel with the tile's
+// input: loaded into registers by `fetch_green`, written to LDS at g_off by
+// `commit_green`.
+template <typename T, int UG>
+struct GreenStage {
+  T a[UG];
+};
+
+template <typename T, int UG>
+__device__ __forceinline__ void fetch_green(GreenStage<T, UG>& gs, const PassDesc& d,
+                                            const TileIdx& ti) {
+  const auto* G = gptr<T>(d.g.G);
+  const int FL = d.g.F_line;
+  const int per = ti.nl * FL;
+  const int64_t fc = fold_index(ti.c, d.g.fold_c);
+#pragma unroll
+  for (int u = 0; u < UG; ++u) {
+    const int r = (int)threadIdx.x + u * kThreads;
+    if (r < per) {
+      const int l = (int)fdiv(r, d.mag_gline);
+      const int j = r - l * FL;
+      gs.a[u] = G[(fc * d.g.F_b + fold_index(ti.b0 + l, d.g.fold_b)) * FL + j];
+    }
+  }
+}
+
+template <typename T, int UG>
+__device__ __forceinline__ void commit_green(const GreenStage<T, UG>& gs, const PassDesc& d,
+                                             const TileIdx& ti, char* smem) {
+  T* gl = reinterpret_cast<T*>(smem + d.g_off);
+  const int per = ti.nl * d.g.F_line;
+#pragma unroll
+  for (int u = 0; u < UG; ++u) {
+    const int r = (int)threadIdx.x + u * kThreads;
+    if (r < per) gl[r] = gs.a[u];
+  }
+}
+
+// Values per thread of the Green stage of a kind (K_ANY: the largest).
+template <typename T, int MC, int KIND>
+constexpr int green_stage() {
+  return fused_of(KIND) || KIND == K_ANY
+             ? green_values((int)sizeof(T), MC, !(KIND == K_F_C2C || KIND == K_F_CURL))
+             : 1;
+}
+
+template <typename T>
+__device__ __forceinline__ Tabs<T> global_tabs(const PassDesc& d) {
+  return {reinterpret_cast<const cpx<T>*>(d.stw), reinterpret_cast<const cpx<T>*>(d.tw)};
+}
+
 template <typename T, int MC, int KIND>
 __device__ __forceinline__ void compute(const PassDesc& d, void* out, const TileIdx& ti,
-                                        char* smem) {
+                                        char* smem, const Tabs<T>& tb) {
   if constexpr (KIND == K_ANY) {
-    if (d.fused) fused_compute<T, MC, K_ANY>(d, out, ti, smem);
-    else plain_compute<T, MC, K_ANY>(d, out, ti, smem);
+    if (d.fused) fused_compute<T, MC, K_ANY>(d, out, ti, smem, tb);
+    else plain_compute<T, MC, K_ANY>(d, out, ti, smem, tb);
   } else if constexpr (fused_of(KIND)) {
-    fused_compute<T, MC, KIND>(d, out, ti, smem);
+    fused_compute<T, MC, KIND>(d, out, ti, smem, tb);
   } else {
-    plain_compute<T, MC, KIND>(d, out, ti, smem);
+    plain_compute<T, MC, KIND>(d, out, ti, smem, tb);
   }
 }
 
@@ -940,12 +1046,16 @@ template <typename T, int MC, typename E, int NCL>
 __device__ __forceinline__ void run_tile_e(const PassDesc& d, const void* in, void* out, int tile,
                                            char* smem) {
   constexpr int U = StageCount<T, E, NCL, MC>::U;
+  constexpr int UG = green_stage<T, MC, K_ANY>();
   RegStage<T, E, U * NCL> v;
+  GreenStage<T, UG> gs;
   const TileIdx ti = tile_index(d, tile);
   fetch<U, NCL, (MC <= 1), E>(v, d, in, ti);
+  if (d.fused) fetch_green<T, UG>(gs, d, ti);
   commit<U, NCL, E>(v, d, ti, smem);
+  if (d.fused) commit_green<T, UG>(gs, d, ti, smem);
   __syncthreads();
-  compute<T, MC, K_ANY>(d, out, ti, smem);
+  compute<T, MC, K_ANY>(d, out, ti, smem, global_tabs<T>(d));
 }
 
 template <typename T, int MC>
@@ -957,45 +1067,78 @@ __device__ __forceinline__ void run_tile(const PassDesc& d, const void* in, void
 }
 
 // Persistent loop over the tiles of a pass: while tile t is transformed in LDS, the
-// input of the next tile of this workgroup is already on its way into registers.
+// input of the next tile of this workgroup (and its Green rows) is already on its way
+// into registers.  The twiddle tables are copied to LDS once, so that the transform
+// issues no global loads: vector-memory loads complete in order, and a global load
+// inside the transform would wait for the whole prefetch.
 template <typename T, int MC, int KIND>
 __device__ __forceinline__ void run_pipelined(const PassDesc& d, const void* in, void* out,
                                               char* smem) {
   using E = typename std::conditional<in_cplx_of(KIND), cpx<T>, T>::type;
   constexpr int NCL = KIND == K_F_CURL ? 3 : 1;
   constexpr int U = StageCount<T, E, NCL, MC>::U;
+  constexpr bool FUSED = fused_of(KIND);
+  constexpr int UG = green_stage<T, MC, KIND>();
   int tile = blockIdx.x;
   const int stride = gridDim.x;
   if (tile >= d.tiles) return;
+  // twiddle tables -> LDS (visible to the transform after the loop's barriers)
+  cpx<T>* lt = reinterpret_cast<cpx<T>*>(smem + d.tab_off);
+  {
+    const auto* stw = gptr<cpx<T>>(d.stw);
+    const auto* tw = gptr<cpx<T>>(d.tw);
+    const int n1 = d.stw_n, n2 = d.stw_n + d.tw_n;
+    for (int i = threadIdx.x; i < n2; i += kThreads) {
+      const auto& w = i < n1 ? stw[i] : tw[i - n1];
+      lt[i] = cpx<T>{w.x, w.y};
+    }
+  }
+  // real-to-real kinds always have their twiddles staged (tw_n = 2M); other kinds do
+  // not read tw in the compile-time kernels
+  const Tabs<T> tb{lt, lt + d.stw_n};
   RegStage<T, E, U * NCL> v;
+  GreenStage<T, UG> gs;
   TileIdx ti = tile_index(d, tile);
   fetch<U, NCL, false, E>(v, d, in, ti);
+  if constexpr (FUSED) fetch_green<T, UG>(gs, d, ti);
   while (true) {
     __syncthreads();  // the previous tile's LDS reads are finished
     commit<U, NCL, E>(v, d, ti, smem);
+    if constexpr (FUSED) commit_green<T, UG>(gs, d, ti, smem);
     __syncthreads();
     const int next = tile + stride;
     TileIdx tn = ti;
     if (next < d.tiles) {
       tn = tile_index(d, next);
       fetch<U, NCL, false, E>(v, d, in, tn);
+      if constexpr (FUSED) fetch_green<T, UG>(gs, d, tn);
     }
-    compute<T, MC, KIND>(d, out, ti, smem);
+    compute<T, MC, KIND>(d, out, ti, smem, tb);
     if (next >= d.tiles) break;
     tile = next;
     ti = tn;
   }
 }
 
-// Tile of a block.  Workgroups are dispatched round-robin over the 8 XCDs; with `xcd`
-// set, consecutive tiles (neighbours in memory along the tile axis) are given to
-// blocks of one XCD so that they share its L2.  The grid then has 8 * ceil(tiles / 8)
-// blocks and the surplus ones exit.
-__device__ __forceinline__ int block_tile(int xcd, int tiles) {
-  const int b = blockIdx.x;
-  if (!xcd) return b;
-  const int per = (tiles + 7) / 8;
-  return (b & 7) * per + (b >> 3);
+// Runtime lengths and long FP64 lines: one tile per workgroup, no register prefetch,
+// tables read from global memory.
+template <typename T, int MC, int KIND>
+__device__ __forceinline__ void run_single(const PassDesc& d, const void* in, void* out,
+                                           char* smem) {
+  if ((int)blockIdx.x >= d.tiles) return;
+  using E = typename std::conditional<in_cplx_of(KIND), cpx<T>, T>::type;
+  constexpr int NCL = KIND == K_F_CURL ? 3 : 1;
+  constexpr int U = StageCount<T, E, NCL, MC>::U;
+  constexpr int UG = green_stage<T, MC, KIND>();
+  RegStage<T, E, U * NCL> v;
+  GreenStage<T, UG> gs;
+  const TileIdx ti = tile_index(d, blockIdx.x);
+  fetch<U, NCL, (MC <= 1), E>(v, d, in, ti);
+  if constexpr (fused_of(KIND)) fetch_green<T, UG>(gs, d, ti);
+  commit<U, NCL, E>(v, d, ti, smem);
+  if constexpr (fused_of(KIND)) commit_green<T, UG>(gs, d, ti, smem);
+  __syncthreads();
+  compute<T, MC, KIND>(d, out, ti, smem, global_tabs<T>(d));
 }
 
 // The descriptor lives in device memory (uniform loads); the buffers of this solve are
@@ -1004,22 +1147,8 @@ template <typename T, int MC, int KIND>
 __global__ __launch_bounds__(kThreads) void pass_kernel(const PassDesc* __restrict__ dp,
                                                         const void* in, void* out) {
   extern __shared__ __align__(16) char smem[];
-  if constexpr (!pipelined_kernel((int)sizeof(T), MC)) {
-    // runtime lengths and long FP64 lines: one tile per workgroup, no register prefetch
-    const PassDesc& d = *dp;
-    if ((int)blockIdx.x >= d.tiles) return;
-    using E = typename std::conditional<in_cplx_of(KIND), cpx<T>, T>::type;
-    constexpr int NCL = KIND == K_F_CURL ? 3 : 1;
-    constexpr int U = StageCount<T, E, NCL, MC>::U;
-    RegStage<T, E, U * NCL> v;
-    const TileIdx ti = tile_index(d, blockIdx.x);
-    fetch<U, NCL, (MC <= 1), E>(v, d, in, ti);
-    commit<U, NCL, E>(v, d, ti, smem);
-    __syncthreads();
-    compute<T, MC, KIND>(d, out, ti, smem);
-  } else {
-    run_pipelined<T, MC, KIND>(*dp, in, out, smem);
-  }
+  if constexpr (!pipelined_kernel((int)sizeof(T), MC)) run_single<T, MC, KIND>(*dp, in, out, smem);
+  else run_pipelined<T, MC, KIND>(*dp, in, out, smem);
 }
 
 // Batched form: tiles of many descriptors of one length class in one launch;

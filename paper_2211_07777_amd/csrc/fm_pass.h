@@ -20,6 +20,12 @@ constexpr int elems_per_thread(int real_bytes, int M) {
   return (real_bytes == 4 || M == kRtLong || M > kMaxFastLen64) ? 16 : 8;
 }
 constexpr int max_radix(int real_bytes) { return real_bytes == 8 ? 8 : 16; }
+// Green's-spectrum values per thread staged with a fused tile (its nl rows of F_line
+// values): complex tiles (one line per FFT, F_line <= M/2 + 1) need at most E/2 + 1,
+// tiles of two real lines per FFT at most E + 1.
+constexpr int green_values(int real_bytes, int M, bool packed) {
+  return packed ? elems_per_thread(real_bytes, M) + 1 : elems_per_thread(real_bytes, M) / 2 + 1;
+}
 // Persistent kernels with register prefetch: compile-time lengths with 8 FP64 values per
 // thread, every compile-time length in FP32.
 constexpr bool pipelined_kernel(int real_bytes, int MC) {
@@ -182,6 +188,14 @@ struct PassDesc {
   int32_t kind;             // PassKind
   int32_t raw_off;          // byte offset of the raw input tile in LDS (0: aliases the
                             // FFT buffer; real-to-real tiles keep it apart)
+  // LDS staging.  Persistent kernels copy the stage twiddle table (stw_n entries) and,
+  // for real-to-real kinds, the first tw_n entries of the 4M table to LDS at tab_off
+  // once per workgroup; fused passes load the tile's Green rows (nl x g.F_line values)
+  // with the tile's input and keep them in LDS at g_off.  The transform itself then
+  // reads no global memory, so the prefetch of the next tile overlaps it.
+  int32_t tab_off, stw_n, tw_n;
+  int32_t g_off;
+  uint64_t mag_gline;       // division by g.F_line
 };
 
 // Sampling description of the Green's function for the spectrum generation (FP64).

@@ -269,6 +269,7 @@ void set_magics(fm::PassDesc* d) {
   d->mag_out = magic(d->out_n);
   d->mag_B = magic(d->B);
   d->mag_spec = magic(d->spec_n);
+  d->mag_gline = magic(d->g.F_line);
 }
 
 int xcd_policy() {
@@ -281,45 +282,82 @@ int xcd_policy() {
 bool pass_in_bounds(const fm::PassDesc& d, int64_t in_size, int64_t out_size, size_t elem);
 int64_t tile_in_span_bytes(const fm::PassDesc& d, size_t elem);
 
+// LDS layout of one tile: the FFT buffer and the raw input tile (real-to-real tiles
+// keep the raw tile, and the fused real spectrum, after the buffer), then the fused
+// tile's Green rows at g_off, then the twiddle tables of the persistent kernels at
+// tab_off.  Returns the total bytes.
+struct TileLds {
+  size_t raw_off, g_off, tab_off, total;
+};
+TileLds tile_lds(const fm::PassDesc& d, int B, size_t elem, int comps, bool fused_r2r) {
+  const int packs = (d.gather == fm::G_CPLX) ? 1 : 2;
+  const size_t cplx = 2 * elem;
+  const size_t in_elem = d.in_cplx ? cplx : elem;
+  const int F = comps * ((B + packs - 1) / packs);
+  const size_t fft = (size_t)F * (d.M + 1) * cplx;
+  const size_t raw = (size_t)comps * B * (d.in_n + 1) * in_elem;
+  TileLds t{};
+  size_t end;
+  if (d.gather == fm::G_R2R) {
+    t.raw_off = round256(fft);
+    size_t extra = raw;
+    if (fused_r2r) extra = std::max(extra, (size_t)B * (d.spec_n + 1) * elem);
+    end = t.raw_off + extra;
+  } else {
+    end = std::max(fft, raw);
+  }
+  if (d.fused) {
+    t.g_off = round256(end);
+    end = t.g_off + (size_t)B * d.g.F_line * elem;
+  }
+  if (d.stw_n + d.tw_n > 0) {
+    t.tab_off = round256(end);
+    end = t.tab_off + (size_t)(d.stw_n + d.tw_n) * cplx;
+  }
+  t.total = round256(end);
+  return t;
+}
+
+// Twiddle entries the persistent kernel of this pass copies to LDS: the stage table,
+// and for real-to-real gathers the first 2M entries of the 4M table (pre- and
+// post-twiddles).
+void set_lds_tables(fm::PassDesc* d, size_t elem) {
+  d->stw_n = d->tw_n = 0;
+  if (!fm::is_fast_len(d->M) || !fm::pipelined_kernel((int)elem, d->M)) return;
+  d->stw_n = fm::stage_table_size(d->M, fm::max_radix((int)elem));
+  if (d->gather == fm::G_R2R) d->tw_n = 2 * d->M;
+}
+
 // Largest tile (lines per workgroup) that fits the register budget and, if possible,
 // the preferred LDS size; otherwise the largest that fits the device's LDS.
 int choose_tile(fm::PassDesc* d, size_t elem, int comps, bool fused_r2r, int nb) {
   const int packs = (d->gather == fm::G_CPLX) ? 1 : 2;
-  const bool r2r = d->gather == fm::G_R2R;
-  const size_t cplx = 2 * elem;
-  const size_t in_elem = d->in_cplx ? cplx : elem;
+  set_lds_tables(d, elem);
   for (const int cap : {fm::kSoftLds, fm::kMaxLds}) {
     int best = 0;
-    size_t best_lds = 0, best_raw_off = 0;
+    TileLds best_lds{};
     for (int B = 1; B <= 64; ++B) {
       const int F = comps * ((B + packs - 1) / packs);
       if ((int64_t)F * d->M > (int64_t)fm::kThreads * fm::elems_per_thread((int)elem, d->M)) break;
       // the register stage must hold the whole input tile (a Hermitian half-spectrum
-      // pair has M + 2 values per FFT line)
+      // pair has M + 2 values per FFT line), and a fused tile's Green rows
       if ((int64_t)B * d->in_n > (int64_t)fm::kThreads * fm::stage_values((int)elem, d->M, d->in_cplx != 0, comps))
         break;
-      const size_t fft = (size_t)F * (d->M + 1) * cplx;
-      const size_t raw = (size_t)comps * B * (d->in_n + 1) * in_elem;
-      size_t lds, raw_off = 0;
-      if (r2r) {
-        // the raw tile (and, fused, the real spectrum after it) sit after the buffer
-        raw_off = round256(fft);
-        size_t extra = raw;
-        if (fused_r2r) extra = std::max(extra, (size_t)B * (d->spec_n + 1) * elem);
-        lds = raw_off + extra;
-      } else {
-        lds = std::max(fft, raw);
-      }
-      if (round256(lds) > (size_t)cap) break;
+      if (d->fused && (int64_t)B * d->g.F_line >
+                          (int64_t)fm::kThreads * fm::green_values((int)elem, d->M, packs == 2))
+        break;
+      const TileLds t = tile_lds(*d, B, elem, comps, fused_r2r);
+      if (t.total > (size_t)cap) break;
       best = B;
-      best_lds = lds;
-      best_raw_off = raw_off;
+      best_lds = t;
       if (B >= nb) break;
     }
     if (best > 0) {
       d->B = best;
-      d->lds_bytes = (int)round256(best_lds);
-      d->raw_off = (int)best_raw_off;
+      d->lds_bytes = (int)best_lds.total;
+      d->raw_off = (int)best_lds.raw_off;
+      d->g_off = (int)best_lds.g_off;
+      d->tab_off = (int)best_lds.tab_off;
       return FM_OK;
     }
   }
@@ -596,7 +634,21 @@ bool pass_in_bounds(const fm::PassDesc& d, int64_t in_size, int64_t out_size, si
   } else if (d.raw_off != 0) {
     return false;
   }
-  if (need > (size_t)d.lds_bytes || d.lds_bytes > fm::kMaxLds) return false;
+  // the staged regions follow the tile, in order, inside lds_bytes
+  size_t end = need;
+  if (d.fused) {
+    if ((int64_t)d.B * d.g.F_line > (int64_t)fm::kThreads * fm::green_values((int)elem, M, packs == 2))
+      return false;
+    if ((size_t)d.g_off < end || d.g_off % 16) return false;
+    end = d.g_off + (size_t)d.B * d.g.F_line * elem;
+  }
+  if (d.stw_n + d.tw_n > 0) {
+    if (d.stw_n != fm::stage_table_size(M, fm::max_radix((int)elem))) return false;
+    if (d.tw_n != 0 && (d.gather != fm::G_R2R || d.tw_n != 2 * M)) return false;
+    if ((size_t)d.tab_off < end || d.tab_off % 16) return false;
+    end = d.tab_off + (size_t)(d.stw_n + d.tw_n) * 2 * elem;
+  }
+  if (end > (size_t)d.lds_bytes || d.lds_bytes > fm::kMaxLds) return false;
   const int nbt = (d.nb + d.B - 1) / d.B;
   if (d.tiles != nbt * d.nc * (comps == 3 ? 1 : d.ncomp)) return false;
   return true;
