@@ -126,6 +126,22 @@ int fm_solve_batched(int count, const fm_plan* plans, const void* const* rhs_dev
                      void* const* out_dev, void* workspace_dev, size_t workspace_bytes,
                      void* hip_stream);
 
+/* A batch prepared once and launched many times: the same work as fm_solve_batched on
+ * fixed buffers.  fm_batch_prepare binds the plans, right-hand sides, outputs and
+ * workspace (arguments as for fm_solve_batched; the workspace must stay allocated and
+ * untouched by others while the batch exists), uploads the batch's descriptor tables
+ * into the workspace and waits for that copy on hip_stream.  fm_batch_run enqueues the
+ * kernels only (no copies, no allocation, no host synchronisation), so it can be
+ * recorded into a HIP graph and replayed; each replay recomputes the outputs from the
+ * current contents of the right-hand sides.  The plans must outlive the batch.
+ * Errors: as fm_solve_batched; FM_E_NULL for a null handle. */
+typedef struct fm_batch_s* fm_batch;
+int fm_batch_prepare(fm_batch* out, int count, const fm_plan* plans, const void* const* rhs_dev,
+                     void* const* out_dev, void* workspace_dev, size_t workspace_bytes,
+                     void* hip_stream);
+int fm_batch_run(fm_batch b, void* hip_stream);
+int fm_batch_destroy(fm_batch b);
+
 /* Workspace for fm_solve_batched: the sum over plans of fm_plan_workspace_bytes,
  * each rounded up to 256 bytes, plus the batch's descriptor table. */
 int fm_batched_workspace_bytes(int count, const fm_plan* plans, size_t* bytes);

@@ -921,6 +921,127 @@ thread_local BatchStaging* g_stage_ptr = nullptr;
 
 }  // namespace
 
+// A prepared batch: FP64 batches hold one launch per pass and length class (descriptor
+// tables in the workspace); FP32 batches hold the per-request buffers of plan-by-plan
+// launches.
+struct fm_batch_s {
+  int prec = 0;
+  std::vector<fm_plan_s*> plans;
+  std::vector<const void*> ins;  // 5 per request
+  std::vector<void*> outs;
+  struct Group {
+    int pass, len_class, first, count, tiles, lds;
+    size_t off_desc, off_pref;
+  };
+  std::vector<Group> groups;
+  char* dev_tables = nullptr;
+};
+
+namespace {
+
+// Work buffers of every request and, for FP64, the grouped descriptor tables (returned
+// in *host, to be copied to b->dev_tables before the first run).
+int build_batch(int count, const fm_plan* plans, const void* const* rhs_dev, void* const* out_dev,
+                void* workspace_dev, size_t workspace_bytes, fm_batch_s* b, std::vector<char>* host) {
+  if (count < 0) return FM_E_ARG;
+  if (!plans || !rhs_dev || !out_dev || !workspace_dev) return FM_E_NULL;
+  size_t need = 0;
+  int rc = fm_batched_workspace_bytes(count, plans, &need);
+  if (rc) return rc;
+  if (workspace_bytes < need) return FM_E_ARG;
+  const int prec = plans[0]->prec;
+  for (int i = 0; i < count; ++i) {
+    if (plans[i]->prec != prec) return FM_E_ARG;
+    if (!rhs_dev[i] || !out_dev[i]) return FM_E_NULL;
+  }
+  b->prec = prec;
+  b->plans.assign(plans, plans + count);
+  b->ins.resize(5 * (size_t)count);
+  b->outs.resize(5 * (size_t)count);
+  char* ws = reinterpret_cast<char*>(workspace_dev);
+  size_t off = 0;
+  for (int i = 0; i < count; ++i) {
+    bind_buffers(plans[i], rhs_dev[i], out_dev[i], ws + off, &b->ins[5 * (size_t)i], &b->outs[5 * (size_t)i]);
+    off += round256(plans[i]->ws_bytes);
+  }
+  host->clear();
+  if (prec == FM_F32) return FM_OK;  // plan by plan, no tables
+  std::vector<fm::PassDesc> all(5 * (size_t)count);
+  for (int i = 0; i < count; ++i)
+    for (int ps = 0; ps < 5; ++ps) {
+      fm::PassDesc& d = all[5 * (size_t)i + ps];
+      d = plans[i]->pass[ps];
+      d.in = b->ins[5 * (size_t)i + ps];
+      d.out = b->outs[5 * (size_t)i + ps];
+    }
+  // group each pass's descriptors by length class: one launch per class and pass
+  std::vector<int> order;
+  size_t table_bytes = 0;
+  for (int ps = 0; ps < 5; ++ps) {
+    std::map<int, std::vector<int>> by_class;
+    for (int i = 0; i < count; ++i) {
+      const fm::PassDesc& d = all[5 * (size_t)i + ps];
+      const int rt = (d.M > fm::kMaxFastLen64) ? fm::kRtLong : fm::kRtShort;
+      by_class[d.stw ? d.M : rt].push_back(i);
+    }
+    for (auto& kv : by_class) {
+      fm_batch_s::Group g{};
+      g.pass = ps;
+      g.len_class = kv.first;
+      g.first = (int)order.size();
+      g.count = (int)kv.second.size();
+      for (int i : kv.second) order.push_back(i);
+      g.off_desc = table_bytes;
+      table_bytes += round256((size_t)g.count * sizeof(fm::PassDesc));
+      g.off_pref = table_bytes;
+      table_bytes += round256((size_t)(g.count + 1) * sizeof(int));
+      b->groups.push_back(g);
+    }
+  }
+  if (off + table_bytes > workspace_bytes) return FM_E_ARG;
+  host->assign(table_bytes, 0);
+  for (fm_batch_s::Group& g : b->groups) {
+    fm::PassDesc* hd = reinterpret_cast<fm::PassDesc*>(host->data() + g.off_desc);
+    int* hp = reinterpret_cast<int*>(host->data() + g.off_pref);
+    int acc = 0, mx = 0;
+    for (int j = 0; j < g.count; ++j) {
+      const int i = order[g.first + j];
+      hd[j] = all[5 * (size_t)i + g.pass];
+      hd[j].xcd = 0;
+      hp[j] = acc;
+      acc += hd[j].tiles;
+      mx = std::max(mx, hd[j].lds_bytes);
+    }
+    hp[g.count] = acc;
+    g.tiles = acc;
+    g.lds = mx;
+  }
+  b->dev_tables = ws + off;
+  return FM_OK;
+}
+
+int run_batch(const fm_batch_s& b, hipStream_t st) {
+  if (b.prec == FM_F32) {
+    for (size_t i = 0; i < b.plans.size(); ++i) {
+      const int rc = launch_all(b.plans[i], &b.ins[5 * i], &b.outs[5 * i], st);
+      if (rc) return rc;
+    }
+    return FM_OK;
+  }
+  for (const fm_batch_s::Group& g : b.groups) {
+    const fm::PassDesc* dd = reinterpret_cast<const fm::PassDesc*>(b.dev_tables + g.off_desc);
+    const int* dp = reinterpret_cast<const int*>(b.dev_tables + g.off_pref);
+    hipError_t e = fm::launch_pass_batched<double>(g.len_class, dd, dp, g.count, g.tiles, g.lds, st);
+    if (e != hipSuccess) {
+      g_last_hip = (int)e;
+      return FM_E_HIP;
+    }
+  }
+  return FM_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* fm_error_string(int status) {
@@ -1101,123 +1222,71 @@ int fm_batched_workspace_bytes(int count, const fm_plan* plans, size_t* bytes) {
 int fm_solve_batched(int count, const fm_plan* plans, const void* const* rhs_dev, void* const* out_dev,
                      void* workspace_dev, size_t workspace_bytes, void* hip_stream) {
   if (count == 0) return FM_OK;
-  if (count < 0) return FM_E_ARG;
-  if (!plans || !rhs_dev || !out_dev || !workspace_dev) return FM_E_NULL;
-  size_t need = 0;
-  int rc = fm_batched_workspace_bytes(count, plans, &need);
+  fm_batch_s b;
+  std::vector<char> host;
+  int rc = build_batch(count, plans, rhs_dev, out_dev, workspace_dev, workspace_bytes, &b, &host);
   if (rc) return rc;
-  if (workspace_bytes < need) return FM_E_ARG;
-  const int prec = plans[0]->prec;
-  for (int i = 0; i < count; ++i) {
-    if (plans[i]->prec != prec) return FM_E_ARG;
-    if (!rhs_dev[i] || !out_dev[i]) return FM_E_NULL;
-  }
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
-  char* ws = reinterpret_cast<char*>(workspace_dev);
-  if (prec == FM_F32) {
-    // FP32 batches run plan by plan with the single-solve kernels, each request in its
-    // own slice of the workspace (the one-launch batched kernels exist in FP64 only)
-    size_t o = 0;
-    for (int i = 0; i < count; ++i) {
-      const void* ins[5];
-      void* outs[5];
-      bind_buffers(plans[i], rhs_dev[i], out_dev[i], ws + o, ins, outs);
-      rc = launch_all(plans[i], ins, outs, st);
-      if (rc) return rc;
-      o += round256(plans[i]->ws_bytes);
+  if (!host.empty()) {
+    // the tables go through pinned host memory, reused once the previous copy finished
+    if (!g_stage_ptr) g_stage_ptr = new (std::nothrow) BatchStaging();
+    if (!g_stage_ptr) return FM_E_NOMEM;
+    BatchStaging& sg = *g_stage_ptr;
+    if (sg.pending) {
+      FM_HIP(hipEventSynchronize(sg.done));
+      sg.pending = false;
     }
-    return FM_OK;
+    if (sg.bytes < host.size()) {
+      if (sg.host) (void)hipHostFree(sg.host);
+      sg.host = nullptr;
+      sg.bytes = 0;
+      if (hipHostMalloc(&sg.host, host.size(), hipHostMallocDefault) != hipSuccess) return FM_E_NOMEM;
+      sg.bytes = host.size();
+    }
+    if (!sg.done) FM_HIP(hipEventCreateWithFlags(&sg.done, hipEventDisableTiming));
+    std::memcpy(sg.host, host.data(), host.size());
+    FM_HIP(hipMemcpyAsync(b.dev_tables, sg.host, host.size(), hipMemcpyHostToDevice, st));
+    FM_HIP(hipEventRecord(sg.done, st));
+    sg.pending = true;
   }
-  // per-request work buffers
-  std::vector<fm::PassDesc> all(5 * (size_t)count);
-  size_t off = 0;
-  for (int i = 0; i < count; ++i) {
-    const void* ins[5];
-    void* outs[5];
-    bind_buffers(plans[i], rhs_dev[i], out_dev[i], ws + off, ins, outs);
-    for (int ps = 0; ps < 5; ++ps) {
-      fm::PassDesc& d = all[5 * (size_t)i + ps];
-      d = plans[i]->pass[ps];
-      d.in = ins[ps];
-      d.out = outs[ps];
-    }
-    off += round256(plans[i]->ws_bytes);
-  }
-  // Group each pass's descriptors by length class (one launch per class and pass) and
-  // stage the tables in pinned host memory (reused once the previous copy finished).
-  struct Group {
-    int pass, len_class, first, count, tiles, lds;
-    size_t off_desc, off_pref;
-  };
-  std::vector<Group> groups;
-  std::vector<int> order;
-  size_t table_bytes = 0;
-  for (int ps = 0; ps < 5; ++ps) {
-    std::map<int, std::vector<int>> by_class;
-    for (int i = 0; i < count; ++i) {
-      const fm::PassDesc& d = all[5 * (size_t)i + ps];
-      const int rt = (prec == FM_F64 && d.M > fm::kMaxFastLen64) ? fm::kRtLong : fm::kRtShort;
-      by_class[d.stw ? d.M : rt].push_back(i);
-    }
-    for (auto& kv : by_class) {
-      Group g{};
-      g.pass = ps;
-      g.len_class = kv.first;
-      g.first = (int)order.size();
-      g.count = (int)kv.second.size();
-      for (int i : kv.second) order.push_back(i);
-      g.off_desc = table_bytes;
-      table_bytes += round256((size_t)g.count * sizeof(fm::PassDesc));
-      g.off_pref = table_bytes;
-      table_bytes += round256((size_t)(g.count + 1) * sizeof(int));
-      groups.push_back(g);
+  return run_batch(b, st);
+}
+
+int fm_batch_prepare(fm_batch* out, int count, const fm_plan* plans, const void* const* rhs_dev,
+                     void* const* out_dev, void* workspace_dev, size_t workspace_bytes,
+                     void* hip_stream) {
+  if (!out) return FM_E_NULL;
+  *out = nullptr;
+  if (count <= 0) return FM_E_ARG;
+  fm_batch_s* b = new (std::nothrow) fm_batch_s();
+  if (!b) return FM_E_NOMEM;
+  std::vector<char> host;
+  int rc = build_batch(count, plans, rhs_dev, out_dev, workspace_dev, workspace_bytes, b, &host);
+  if (rc == FM_OK && !host.empty()) {
+    // uploaded once, synchronously: fm_batch_run then only launches kernels
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    hipError_t e = hipMemcpyAsync(b->dev_tables, host.data(), host.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+      g_last_hip = (int)e;
+      rc = FM_E_HIP;
     }
   }
-  if (off + table_bytes > workspace_bytes) return FM_E_ARG;
-  if (!g_stage_ptr) g_stage_ptr = new (std::nothrow) BatchStaging();
-  if (!g_stage_ptr) return FM_E_NOMEM;
-  BatchStaging& sg = *g_stage_ptr;
-  if (sg.pending) {
-    FM_HIP(hipEventSynchronize(sg.done));
-    sg.pending = false;
+  if (rc) {
+    delete b;
+    return rc;
   }
-  if (sg.bytes < table_bytes) {
-    if (sg.host) (void)hipHostFree(sg.host);
-    sg.host = nullptr;
-    sg.bytes = 0;
-    if (hipHostMalloc(&sg.host, table_bytes, hipHostMallocDefault) != hipSuccess) return FM_E_NOMEM;
-    sg.bytes = table_bytes;
-  }
-  if (!sg.done) FM_HIP(hipEventCreateWithFlags(&sg.done, hipEventDisableTiming));
-  char* host = reinterpret_cast<char*>(sg.host);
-  char* dev = ws + off;
-  for (Group& g : groups) {
-    fm::PassDesc* hd = reinterpret_cast<fm::PassDesc*>(host + g.off_desc);
-    int* hp = reinterpret_cast<int*>(host + g.off_pref);
-    int acc = 0, mx = 0;
-    for (int j = 0; j < g.count; ++j) {
-      const int i = order[g.first + j];
-      hd[j] = all[5 * (size_t)i + g.pass];
-      hd[j].xcd = 0;
-      hp[j] = acc;
-      acc += hd[j].tiles;
-      mx = std::max(mx, hd[j].lds_bytes);
-    }
-    hp[g.count] = acc;
-    g.tiles = acc;
-    g.lds = mx;
-  }
-  FM_HIP(hipMemcpyAsync(dev, host, table_bytes, hipMemcpyHostToDevice, st));
-  FM_HIP(hipEventRecord(sg.done, st));
-  sg.pending = true;
-  for (const Group& g : groups) {
-    const fm::PassDesc* dd = reinterpret_cast<const fm::PassDesc*>(dev + g.off_desc);
-    const int* dp = reinterpret_cast<const int*>(dev + g.off_pref);
-    hipError_t e = (prec == FM_F64)
-                       ? fm::launch_pass_batched<double>(g.len_class, dd, dp, g.count, g.tiles, g.lds, st)
-                       : fm::launch_pass_batched<float>(g.len_class, dd, dp, g.count, g.tiles, g.lds, st);
-    if (e != hipSuccess) { g_last_hip = (int)e; return FM_E_HIP; }
-  }
+  *out = b;
+  return FM_OK;
+}
+
+int fm_batch_run(fm_batch b, void* hip_stream) {
+  if (!b) return FM_E_NULL;
+  return run_batch(*b, reinterpret_cast<hipStream_t>(hip_stream));
+}
+
+int fm_batch_destroy(fm_batch b) {
+  delete b;
   return FM_OK;
 }
 

@@ -23,7 +23,7 @@ CLASS_NAMES = ["P", "EE", "OO", "EO", "OE", "UU", "EU", "OU", "UE", "UO"]
 EXPORTED = [
     "fm_plan_create", "fm_plan_destroy", "fm_plan_workspace_bytes", "fm_plan_shape",
     "fm_solve", "fm_solve_passes", "fm_solve_batched", "fm_batched_workspace_bytes", "fm_plan_inspect",
-    "fm_error_string", "fm_last_hip_error",
+    "fm_error_string", "fm_last_hip_error", "fm_batch_prepare", "fm_batch_run", "fm_batch_destroy",
 ]
 
 
@@ -75,6 +75,10 @@ def library():
     L.fm_batched_workspace_bytes.argtypes = [ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_size_t)]
     L.fm_plan_inspect.argtypes = [ip, dp, ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                   ctypes.c_int, ctypes.POINTER(_Info)]
+    L.fm_batch_prepare.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                   ctypes.POINTER(vp), vp, ctypes.c_size_t, vp]
+    L.fm_batch_run.argtypes = [vp, vp]
+    L.fm_batch_destroy.argtypes = [vp]
     L.fm_error_string.argtypes = [ctypes.c_int]
     L.fm_error_string.restype = ctypes.c_char_p
     L.fm_last_hip_error.restype = ctypes.c_int
@@ -227,3 +231,42 @@ def solve_batched(plans, rhs, outs, workspace, stream=None):
     _check(library().fm_solve_batched(n, P, R, O, ctypes.c_void_p(workspace.data_ptr()), nbytes,
                                       _stream_ptr(stream)), "fm_solve_batched")
     return outs
+
+
+class Batch:
+    """A batch bound to fixed tensors (fm_batch_prepare); run() only enqueues kernels,
+    so it can be captured in a HIP graph (torch.cuda.graph) and replayed."""
+
+    def __init__(self, plans, rhs, outs, workspace, stream=None):
+        n = len(plans)
+        if not (len(rhs) == len(outs) == n) or n == 0:
+            raise ValueError("plans, rhs and outs must have the same, nonzero length")
+        for p, r, o in zip(plans, rhs, outs):
+            p._check_tensor(r, "rhs")
+            p._check_tensor(o, "out")
+        # keep the plans and buffers alive as long as the batch
+        self._keep = (list(plans), list(rhs), list(outs), workspace)
+        P = (ctypes.c_void_p * n)(*[p._h.value for p in plans])
+        R = (ctypes.c_void_p * n)(*[r.data_ptr() for r in rhs])
+        O = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+        handle = ctypes.c_void_p()
+        nbytes = workspace.numel() * workspace.element_size()
+        _check(library().fm_batch_prepare(ctypes.byref(handle), n, P, R, O, ctypes.c_void_p(workspace.data_ptr()),
+                                          nbytes, _stream_ptr(stream)), "fm_batch_prepare")
+        self._h = handle
+
+    def run(self, stream=None):
+        _check(library().fm_batch_run(self._h, _stream_ptr(stream)), "fm_batch_run")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            library().fm_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        if sys.is_finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
