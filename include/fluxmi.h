@@ -126,6 +126,18 @@ int fm_solve_batched(int count, const fm_plan* plans, const void* const* rhs_dev
                      void* const* out_dev, void* workspace_dev, size_t workspace_bytes,
                      void* hip_stream);
 
+/* Autotuner: times every pass of the plan on the device for candidate tilings (lines
+ * per tile and a persistent or one-tile-per-workgroup grid), keeps the fastest valid one
+ * per pass in the plan, and uses it for every later solve.  Results can change at the
+ * rounding level only: two real lines share one complex FFT, and which lines are paired
+ * follows the tiling.  workspace_dev as for fm_solve (NULL: the plan's own);
+ * the call allocates two scratch arrays of the user shape and synchronises hip_stream.
+ * Not to be called while solves with this plan are in flight. */
+int fm_plan_tune(fm_plan p, void* workspace_dev, void* hip_stream);
+
+/* The plan's current tiling per pass: lines per tile, tiles, persistent grid (1/0). */
+int fm_plan_tiling(fm_plan p, int lines_per_tile[5], int tiles[5], int persist[5]);
+
 /* A batch prepared once and launched many times: the same work as fm_solve_batched on
  * fixed buffers.  fm_batch_prepare binds the plans, right-hand sides, outputs and
  * workspace (arguments as for fm_solve_batched; the workspace must stay allocated and

@@ -55,7 +55,7 @@ static hipError_t launch_kind(const PassDesc& d, const PassDesc* dev, const void
     const char* e = std::getenv("FLUXMI_PERSISTENT");
     return e == nullptr || std::atoi(e) != 0;
   }();
-  const int grid = (!persistent || d.tiles < resident[slot]) ? d.tiles : resident[slot];
+  const int grid = (!persistent || !d.persist || d.tiles < resident[slot]) ? d.tiles : resident[slot];
   hipLaunchKernelGGL((pass_kernel<FM_T, FM_MC, KIND>), dim3(grid), dim3(kThreads), d.lds_bytes, st,
                      dev, in, out);
   return hipGetLastError();

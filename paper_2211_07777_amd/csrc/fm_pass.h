@@ -184,7 +184,8 @@ struct PassDesc {
   // n / d = (n * mag) >> 32 for n * d < 2^32
   uint64_t mag_in, mag_out, mag_B, mag_spec;
   const void* stw;          // stage twiddle table of a compile-time length (or null)
-  int32_t xcd;              // spread consecutive tiles over one XCD at a time
+  int32_t persist;          // compile-time-length kernels: 1 = as many workgroups as fit
+                            // on the device, each looping over tiles; 0 = one tile each
   int32_t kind;             // PassKind
   int32_t raw_off;          // byte offset of the raw input tile in LDS (0: aliases the
                             // FFT buffer; real-to-real tiles keep it apart)

@@ -272,13 +272,6 @@ void set_magics(fm::PassDesc* d) {
   d->mag_gline = magic(d->g.F_line);
 }
 
-int xcd_policy() {
-  static int v = [] {
-    const char* e = std::getenv("FLUXMI_XCD");
-    return e ? std::atoi(e) : 1;
-  }();
-  return v;
-}
 bool pass_in_bounds(const fm::PassDesc& d, int64_t in_size, int64_t out_size, size_t elem);
 int64_t tile_in_span_bytes(const fm::PassDesc& d, size_t elem);
 
@@ -330,13 +323,13 @@ void set_lds_tables(fm::PassDesc* d, size_t elem) {
 
 // Largest tile (lines per workgroup) that fits the register budget and, if possible,
 // the preferred LDS size; otherwise the largest that fits the device's LDS.
-int choose_tile(fm::PassDesc* d, size_t elem, int comps, bool fused_r2r, int nb) {
+int choose_tile(fm::PassDesc* d, size_t elem, int comps, bool fused_r2r, int nb, int bmax = 64) {
   const int packs = (d->gather == fm::G_CPLX) ? 1 : 2;
   set_lds_tables(d, elem);
   for (const int cap : {fm::kSoftLds, fm::kMaxLds}) {
     int best = 0;
     TileLds best_lds{};
-    for (int B = 1; B <= 64; ++B) {
+    for (int B = 1; B <= bmax; ++B) {
       const int F = comps * ((B + packs - 1) / packs);
       if ((int64_t)F * d->M > (int64_t)fm::kThreads * fm::elems_per_thread((int)elem, d->M)) break;
       // the register stage must hold the whole input tile (a Hermitian half-spectrum
@@ -856,7 +849,7 @@ int build_plan(fm_plan_s* p) {
     if (rc2) return rc2;
     d.tiles = ((d.nb + d.B - 1) / d.B) * d.nc * (fused_curl ? 1 : p->ncomp);
     set_magics(&d);
-    d.xcd = (xcd_policy() && d.tiles >= 64) ? 1 : 0;
+    d.persist = 1;
   }
   for (int i = 0; i < 5; ++i) p->pass[i].kind = pass_kind(p->pass[i]);
   const int64_t sizes_in[5] = {p->Vu, p->V1, p->V2, p->V2, p->V1};
@@ -1007,7 +1000,6 @@ int build_batch(int count, const fm_plan* plans, const void* const* rhs_dev, voi
     for (int j = 0; j < g.count; ++j) {
       const int i = order[g.first + j];
       hd[j] = all[5 * (size_t)i + g.pass];
-      hd[j].xcd = 0;
       hp[j] = acc;
       acc += hd[j].tiles;
       mx = std::max(mx, hd[j].lds_bytes);
@@ -1250,6 +1242,115 @@ int fm_solve_batched(int count, const fm_plan* plans, const void* const* rhs_dev
     sg.pending = true;
   }
   return run_batch(b, st);
+}
+
+// A pass re-tiled with at most bmax lines per tile; false if no such tiling is valid
+// for this plan (the persistent kernels address a tile with 32-bit offsets).
+bool retile(const fm_plan_s* p, int i, int bmax, int persist, fm::PassDesc* out) {
+  fm::PassDesc d = p->pass[i];
+  const bool fused_curl = (i == 2) && p->kind == FM_BIOT_SAVART;
+  if (choose_tile(&d, p->elem, fused_curl ? 3 : 1, (i == 2) && d.gather == fm::G_R2R, d.nb, bmax))
+    return false;
+  d.tiles = ((d.nb + d.B - 1) / d.B) * d.nc * (fused_curl ? 1 : p->ncomp);
+  set_magics(&d);
+  d.persist = persist;
+  if (d.stw && tile_in_span_bytes(d, p->elem) >= (int64_t(1) << 32)) return false;
+  const int64_t sizes_in[5] = {p->Vu, p->V1, p->V2, p->V2, p->V1};
+  const int64_t sizes_out[5] = {p->V1, p->V2, p->V2, p->V1, p->Vu};
+  if (!pass_in_bounds(d, sizes_in[i], sizes_out[i], p->elem)) return false;
+  *out = d;
+  return true;
+}
+
+int fm_plan_tune(fm_plan p, void* workspace_dev, void* hip_stream) {
+  if (!p) return FM_E_NULL;
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  char* ws = reinterpret_cast<char*>(workspace_dev);
+  if (!ws) {
+    if (!p->ws_internal && hipMalloc(&p->ws_internal, p->ws_bytes) != hipSuccess) return FM_E_NOMEM;
+    ws = reinterpret_cast<char*>(p->ws_internal);
+  }
+  // scratch right-hand side and output (their values do not change the timing)
+  const size_t ubytes = (size_t)p->Vu * p->ncomp * p->elem;
+  void* rhs = nullptr;
+  void* out = nullptr;
+  if (hipMalloc(&rhs, ubytes) != hipSuccess) return FM_E_NOMEM;
+  if (hipMalloc(&out, ubytes) != hipSuccess) {
+    (void)hipFree(rhs);
+    return FM_E_NOMEM;
+  }
+  int rc = FM_OK;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t he = hipMemsetAsync(rhs, 0, ubytes, st);
+  if (he == hipSuccess) he = hipEventCreate(&e0);
+  if (he == hipSuccess) he = hipEventCreate(&e1);
+  const void* ins[5];
+  void* outs[5];
+  bind_buffers(p, rhs, out, ws, ins, outs);
+  // time one pass with descriptor d (uploaded to the plan's device slot): best of reps
+  auto time_pass = [&](int i, const fm::PassDesc& d, float* ms) -> hipError_t {
+    hipError_t e = hipMemcpyAsync(p->dpass + i, &d, sizeof(fm::PassDesc), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(st);
+    float best = 1e30f;
+    for (int r = 0; r < 4 && e == hipSuccess; ++r) {
+      e = hipEventRecord(e0, st);
+      if (e == hipSuccess)
+        e = (p->prec == FM_F64) ? fm::launch_pass<double>(d, p->dpass + i, ins[i], outs[i], st)
+                                : fm::launch_pass<float>(d, p->dpass + i, ins[i], outs[i], st);
+      if (e == hipSuccess) e = hipEventRecord(e1, st);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float t = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+      if (r > 0) best = std::min(best, t);  // the first run warms up
+    }
+    *ms = best;
+    return e;
+  };
+  for (int i = 0; i < 5 && he == hipSuccess; ++i) {
+    fm::PassDesc best = p->pass[i];
+    float best_ms = 0.f;
+    he = time_pass(i, best, &best_ms);
+    std::vector<std::pair<int, int>> seen{{best.B, best.persist}};
+    for (const int bmax : {64, 32, 16, 8, 4, 2, 1}) {
+      for (const int persist : {1, 0}) {
+        fm::PassDesc d;
+        if (he != hipSuccess || !retile(p, i, bmax, persist, &d)) continue;
+        const std::pair<int, int> key{d.B, d.persist};
+        if (std::find(seen.begin(), seen.end(), key) != seen.end()) continue;
+        seen.push_back(key);
+        float ms = 0.f;
+        he = time_pass(i, d, &ms);
+        if (he == hipSuccess && ms < best_ms) {
+          best_ms = ms;
+          best = d;
+        }
+      }
+    }
+    p->pass[i] = best;
+    if (he == hipSuccess)
+      he = hipMemcpyAsync(p->dpass + i, &p->pass[i], sizeof(fm::PassDesc), hipMemcpyHostToDevice, st);
+  }
+  if (he == hipSuccess) he = hipStreamSynchronize(st);
+  if (he != hipSuccess) {
+    g_last_hip = (int)he;
+    rc = FM_E_HIP;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(rhs);
+  (void)hipFree(out);
+  return rc;
+}
+
+int fm_plan_tiling(fm_plan p, int lines_per_tile[5], int tiles[5], int persist[5]) {
+  if (!p || !lines_per_tile || !tiles || !persist) return FM_E_NULL;
+  for (int i = 0; i < 5; ++i) {
+    lines_per_tile[i] = p->pass[i].B;
+    tiles[i] = p->pass[i].tiles;
+    persist[i] = p->pass[i].persist;
+  }
+  return FM_OK;
 }
 
 int fm_batch_prepare(fm_batch* out, int count, const fm_plan* plans, const void* const* rhs_dev,

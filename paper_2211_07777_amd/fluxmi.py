@@ -24,6 +24,7 @@ EXPORTED = [
     "fm_plan_create", "fm_plan_destroy", "fm_plan_workspace_bytes", "fm_plan_shape",
     "fm_solve", "fm_solve_passes", "fm_solve_batched", "fm_batched_workspace_bytes", "fm_plan_inspect",
     "fm_error_string", "fm_last_hip_error", "fm_batch_prepare", "fm_batch_run", "fm_batch_destroy",
+    "fm_plan_tune", "fm_plan_tiling",
 ]
 
 
@@ -78,6 +79,8 @@ def library():
     L.fm_batch_prepare.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                    ctypes.POINTER(vp), vp, ctypes.c_size_t, vp]
     L.fm_batch_run.argtypes = [vp, vp]
+    L.fm_plan_tune.argtypes = [vp, vp, vp]
+    L.fm_plan_tiling.argtypes = [vp, ip, ip, ip]
     L.fm_batch_destroy.argtypes = [vp]
     L.fm_error_string.argtypes = [ctypes.c_int]
     L.fm_error_string.restype = ctypes.c_char_p
@@ -192,6 +195,18 @@ class Plan:
                                          ctypes.c_void_p(out.data_ptr()), ws, int(first), int(last),
                                          _stream_ptr(stream)), "fm_solve_passes")
         return out
+
+    def tune(self, workspace=None, stream=None):
+        """Autotune the tiling of every pass on the device (fm_plan_tune)."""
+        ws = ctypes.c_void_p(0 if workspace is None else workspace.data_ptr())
+        _check(library().fm_plan_tune(self._h, ws, _stream_ptr(stream)), "fm_plan_tune")
+        return self.tiling()
+
+    def tiling(self):
+        """(lines per tile, tiles, persistent grid) of the five passes."""
+        b, t, q = (ctypes.c_int * 5)(), (ctypes.c_int * 5)(), (ctypes.c_int * 5)()
+        _check(library().fm_plan_tiling(self._h, b, t, q), "fm_plan_tiling")
+        return {"lines_per_tile": list(b), "tiles": list(t), "persistent": list(q)}
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
