@@ -135,6 +135,10 @@ int fm_solve_batched(int count, const fm_plan* plans, const void* const* rhs_dev
  * Not to be called while solves with this plan are in flight. */
 int fm_plan_tune(fm_plan p, void* workspace_dev, void* hip_stream);
 
+/* Device memory held by the plan's tables (Green's spectrum, twiddles, descriptors),
+ * not counting its own workspace. */
+int fm_plan_device_bytes(fm_plan p, size_t* bytes);
+
 /* The plan's current tiling per pass: lines per tile, tiles, persistent grid (1/0). */
 int fm_plan_tiling(fm_plan p, int lines_per_tile[5], int tiles[5], int persist[5]);
 
@@ -153,6 +157,39 @@ int fm_batch_prepare(fm_batch* out, int count, const fm_plan* plans, const void*
                      void* hip_stream);
 int fm_batch_run(fm_batch b, void* hip_stream);
 int fm_batch_destroy(fm_batch b);
+
+/* Serving loop (continuous admission).  A server owns one device arena of
+ * workspace_budget_bytes for the workspaces of running requests and a cache of plans
+ * whose tables may use up to plan_budget_bytes (least recently used plans with no
+ * waiting or running request are destroyed beyond that).  Each request is one solve
+ * (fm_solve semantics; rhs_dev / out_dev are the caller's and must stay valid until the
+ * request has finished).  Requests wait in FIFO order until one of `slots` device
+ * streams and their workspace are free; then they run, overlapping on the device with
+ * the other running requests.  fm_server_progress retires finished requests, admits
+ * waiting ones and returns the finished tickets (in completion order); it never
+ * blocks.  fm_server_wait_all blocks until every submitted request has finished.
+ * tune_plans != 0 autotunes each new plan (fm_plan_tune).  One host thread drives a
+ * server.  Errors: FM_E_ARG (slots outside 1..64, zero budget), FM_E_NOMEM (arena, or a
+ * request whose workspace exceeds the whole budget), FM_E_HIP, and those of
+ * fm_plan_create / fm_solve for a request. */
+typedef struct fm_server_s* fm_server;
+typedef struct {
+  long long submitted, finished;               /* requests */
+  long long plan_hits, plan_misses, plan_evictions;
+  size_t peak_workspace_bytes;                 /* arena bytes in use, maximum */
+  int peak_inflight;                           /* requests running at once, maximum */
+  int cached_plans, waiting, running;          /* now */
+  size_t plan_bytes;                           /* device bytes of the cached plans, now */
+} fm_server_stats;
+int fm_server_create(fm_server* out, size_t workspace_budget_bytes, size_t plan_budget_bytes,
+                     int slots, int tune_plans);
+int fm_server_submit(fm_server s, const int n[3], const double h[3], const int bc[3][2], int layout,
+                     int green, int prec, int kind, int ncomp, const void* rhs_dev, void* out_dev,
+                     long long* ticket);
+int fm_server_progress(fm_server s, long long* finished, int max_finished, int* n_finished);
+int fm_server_wait_all(fm_server s);
+int fm_server_get_stats(fm_server s, fm_server_stats* stats);
+int fm_server_destroy(fm_server s);
 
 /* Workspace for fm_solve_batched: the sum over plans of fm_plan_workspace_bytes,
  * each rounded up to 256 bytes, plus the batch's descriptor table. */

@@ -5,6 +5,6 @@ this package only marshals arguments (torch tensors for device memory and stream
 """
 from .fluxmi import (  # noqa: F401
     CELL, NODE, EVEN, ODD, PER, UNB, F64, F32, POISSON, BIOT_SAVART, CHAT2, CHAT2_VOL,
-    FluxmiError, Plan, Batch, plan_inspect, solve_batched, batched_workspace_bytes, library,
+    FluxmiError, Plan, Batch, Server, plan_inspect, solve_batched, batched_workspace_bytes, library,
     error_string,
 )

@@ -37,11 +37,12 @@ def _units():
     units.append((os.path.join(CSRC, "fm_inst.hip"), "inst_double_long.o", ["-DFM_T=double", "-DFM_MC=1"]))
     units.append((os.path.join(CSRC, "fm_gen.hip"), "gen.o", []))
     units.append((os.path.join(CSRC, "fm_plan.cpp"), "plan.o", []))
+    units.append((os.path.join(CSRC, "fm_serve.cpp"), "serve.o", []))
     return units
 
 
 def _sources():
-    return [os.path.join(CSRC, f) for f in ("fm_inst.hip", "fm_gen.hip", "fm_plan.cpp")] + \
+    return [os.path.join(CSRC, f) for f in ("fm_inst.hip", "fm_gen.hip", "fm_plan.cpp", "fm_serve.cpp")] + \
         [os.path.join(CSRC, h) for h in HEADERS] + [os.path.join(os.path.dirname(HERE), "include", "fluxmi.h")]
 
 

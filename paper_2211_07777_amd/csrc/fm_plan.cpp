@@ -252,6 +252,7 @@ struct fm_plan_s {
   std::map<int, void*> tw64;
   void* ws_internal = nullptr;
   int device = 0;
+  size_t table_bytes = 0;  // device memory of the plan's tables (Green, twiddles, descriptors)
 };
 
 namespace {
@@ -415,6 +416,7 @@ int make_tables_and_green(fm_plan_s* p, hipStream_t st) {
     void* ptr = nullptr;
     if (hipMalloc(&ptr, sizeof(T) * 2 * 4 * (size_t)M) != hipSuccess) return FM_E_NOMEM;
     p->tw[M] = ptr;
+    p->table_bytes += sizeof(T) * 2 * 4 * (size_t)M;
     FM_HIP(fm::launch_twiddles<T>(ptr, M, st));
   }
   for (int i = 0; i < 5; ++i) p->pass[i].tw = p->tw[p->pass[i].M];
@@ -428,6 +430,7 @@ int make_tables_and_green(fm_plan_s* p, hipStream_t st) {
       const size_t n = (size_t)std::max(1, fm::stage_table_size(M, fm::max_radix((int)sizeof(T))));
       if (hipMalloc(&ptr, sizeof(T) * 2 * n) != hipSuccess) return FM_E_NOMEM;
       p->stw[M] = ptr;
+      p->table_bytes += sizeof(T) * 2 * n;
       FM_HIP(fm::launch_stage_twiddles<T>(ptr, M, st));
     }
     p->pass[i].stw = p->stw[M];
@@ -521,14 +524,20 @@ int make_tables_and_green(fm_plan_s* p, hipStream_t st) {
   }
   if (rc == FM_OK) {
     const int64_t nG = (int64_t)F[0] * F[1] * F[2];
-    if (hipMalloc(&p->G, sizeof(T) * nG) != hipSuccess) rc = FM_E_NOMEM;
-    else FM_HIP(fm::launch_green_final<T>(p->G, S, F, Fs, off, scale, st));
+    if (hipMalloc(&p->G, sizeof(T) * nG) != hipSuccess) {
+      rc = FM_E_NOMEM;
+    } else {
+      p->table_bytes += sizeof(T) * nG;
+      FM_HIP(fm::launch_green_final<T>(p->G, S, F, Fs, off, scale, st));
+    }
   }
   // the five pass descriptors, now complete, go to device memory
   for (int i = 0; i < 5; ++i) p->pass[i].g.G = p->G;
   if (rc == FM_OK) {
     if (hipMalloc(&p->dpass, sizeof(fm::PassDesc) * 5) != hipSuccess) rc = FM_E_NOMEM;
-    else FM_HIP(hipMemcpyAsync(p->dpass, p->pass, sizeof(fm::PassDesc) * 5, hipMemcpyHostToDevice, st));
+    else p->table_bytes += sizeof(fm::PassDesc) * 5;
+    if (rc == FM_OK)
+      FM_HIP(hipMemcpyAsync(p->dpass, p->pass, sizeof(fm::PassDesc) * 5, hipMemcpyHostToDevice, st));
   }
   hipError_t e = hipStreamSynchronize(st);
   (void)hipFree(gdev);
@@ -1034,6 +1043,10 @@ int run_batch(const fm_batch_s& b, hipStream_t st) {
 
 }  // namespace
 
+namespace fm {
+void set_last_hip_error(int e) { g_last_hip = e; }
+}  // namespace fm
+
 extern "C" {
 
 const char* fm_error_string(int status) {
@@ -1341,6 +1354,12 @@ int fm_plan_tune(fm_plan p, void* workspace_dev, void* hip_stream) {
   (void)hipFree(rhs);
   (void)hipFree(out);
   return rc;
+}
+
+int fm_plan_device_bytes(fm_plan p, size_t* bytes) {
+  if (!p || !bytes) return FM_E_NULL;
+  *bytes = p->table_bytes;
+  return FM_OK;
 }
 
 int fm_plan_tiling(fm_plan p, int lines_per_tile[5], int tiles[5], int persist[5]) {

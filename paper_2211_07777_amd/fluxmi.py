@@ -24,8 +24,18 @@ EXPORTED = [
     "fm_plan_create", "fm_plan_destroy", "fm_plan_workspace_bytes", "fm_plan_shape",
     "fm_solve", "fm_solve_passes", "fm_solve_batched", "fm_batched_workspace_bytes", "fm_plan_inspect",
     "fm_error_string", "fm_last_hip_error", "fm_batch_prepare", "fm_batch_run", "fm_batch_destroy",
-    "fm_plan_tune", "fm_plan_tiling",
+    "fm_plan_tune", "fm_plan_tiling", "fm_plan_device_bytes",
+    "fm_server_create", "fm_server_submit", "fm_server_progress", "fm_server_wait_all",
+    "fm_server_get_stats", "fm_server_destroy",
 ]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_longlong), ("finished", ctypes.c_longlong),
+                ("plan_hits", ctypes.c_longlong), ("plan_misses", ctypes.c_longlong),
+                ("plan_evictions", ctypes.c_longlong), ("peak_workspace_bytes", ctypes.c_size_t),
+                ("peak_inflight", ctypes.c_int), ("cached_plans", ctypes.c_int), ("waiting", ctypes.c_int),
+                ("running", ctypes.c_int), ("plan_bytes", ctypes.c_size_t)]
 
 
 class FluxmiError(RuntimeError):
@@ -81,6 +91,16 @@ def library():
     L.fm_batch_run.argtypes = [vp, vp]
     L.fm_plan_tune.argtypes = [vp, vp, vp]
     L.fm_plan_tiling.argtypes = [vp, ip, ip, ip]
+    L.fm_plan_device_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    L.fm_server_create.argtypes = [ctypes.POINTER(vp), ctypes.c_size_t, ctypes.c_size_t, ctypes.c_int,
+                                   ctypes.c_int]
+    L.fm_server_submit.argtypes = [vp, ip, dp, ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                   ctypes.c_int, vp, vp, ctypes.POINTER(ctypes.c_longlong)]
+    L.fm_server_progress.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.c_int,
+                                     ctypes.POINTER(ctypes.c_int)]
+    L.fm_server_wait_all.argtypes = [vp]
+    L.fm_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    L.fm_server_destroy.argtypes = [vp]
     L.fm_batch_destroy.argtypes = [vp]
     L.fm_error_string.argtypes = [ctypes.c_int]
     L.fm_error_string.restype = ctypes.c_char_p
@@ -277,6 +297,66 @@ class Batch:
         if getattr(self, "_h", None) is not None and self._h.value:
             library().fm_batch_destroy(self._h)
             self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        if sys.is_finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Serving loop (fm_server_*): requests are admitted as device streams and workspace
+    (within the HBM budget) free up; plans are cached on the device.  One host thread."""
+
+    def __init__(self, workspace_budget_bytes, plan_budget_bytes, slots=8, tune_plans=False):
+        handle = ctypes.c_void_p()
+        _check(library().fm_server_create(ctypes.byref(handle), int(workspace_budget_bytes),
+                                          int(plan_budget_bytes), int(slots), int(bool(tune_plans))),
+               "fm_server_create")
+        self._h = handle
+        self._keep = {}  # ticket -> (rhs, out): alive until finished
+
+    def submit(self, n, h, bc, layout, rhs, out, prec=F32, green=CHAT2, kind=POISSON, ncomp=1):
+        """Enqueue one solve; returns its ticket."""
+        import torch
+        dt = torch.float64 if prec == F64 else torch.float32
+        for t, name in ((rhs, "rhs"), (out, "out")):
+            if not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+                raise ValueError(f"{name}: need a contiguous {dt} GPU tensor")
+        n3, h3, b6 = _args(n, h, bc)
+        ticket = ctypes.c_longlong()
+        _check(library().fm_server_submit(self._h, n3, h3, b6, layout, green, prec, kind, ncomp,
+                                          ctypes.c_void_p(rhs.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                          ctypes.byref(ticket)), "fm_server_submit")
+        self._keep[ticket.value] = (rhs, out)
+        return ticket.value
+
+    def progress(self, max_finished=4096):
+        """Admit and retire; returns the tickets finished since the last call."""
+        buf = (ctypes.c_longlong * max_finished)()
+        n = ctypes.c_int()
+        _check(library().fm_server_progress(self._h, buf, max_finished, ctypes.byref(n)), "fm_server_progress")
+        done = list(buf[:n.value])
+        for t in done:
+            self._keep.pop(t, None)
+        return done
+
+    def wait_all(self):
+        _check(library().fm_server_wait_all(self._h), "fm_server_wait_all")
+
+    def stats(self):
+        st = ServerStats()
+        _check(library().fm_server_get_stats(self._h, ctypes.byref(st)), "fm_server_get_stats")
+        return {name: getattr(st, name) for name, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            library().fm_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            self._keep.clear()
 
     def __del__(self):
         if sys.is_finalizing():

@@ -147,14 +147,16 @@ def draw_axis_bc(rng):
             return [int(left), int(right)]
 
 
-def serving_stream(count=2000, qps=1000.0, seed=DEFAULT_SEED, h=1.0 / 64):
-    """List of request dicts: n (x, y, z), h, bc, layout, arrival time (s), seed."""
+def serving_stream(count=2000, qps=1000.0, seed=DEFAULT_SEED, h=1.0 / 64, edges=None):
+    """List of request dicts: n (x, y, z), h, bc, layout, arrival time (s), seed.
+    Grid edges are drawn from `edges` (default: the serving edges 32 ... 192)."""
     rng = np.random.default_rng(seed)
+    edges = SERVING_EDGES if edges is None else edges
     t = 0.0
     reqs = []
     for i in range(count):
         t += rng.exponential(1.0 / qps)
-        n = [int(rng.choice(SERVING_EDGES)) for _ in range(3)]
+        n = [int(rng.choice(edges)) for _ in range(3)]
         bc = [draw_axis_bc(rng) for _ in range(3)]
         layout = int(rng.integers(0, 2))
         reqs.append({"id": i, "n": n, "h": [h, h, h], "bc": bc, "layout": layout, "t": t,
