@@ -113,6 +113,135 @@ def calibration_copy(mib):
     return n * 4
 
 
+def run_batched(count, reps):
+    """Many small solves: a prepared FP32 batch captured in a HIP graph and replayed, the
+    FP64 one-launch batch, and plain FP64 solves one at a time (solves/s)."""
+    import torch
+    import paper_2211_07777_amd as F
+    from paper_2211_07777_amd import workloads as W
+    reqs = W.serving_stream(count=count, qps=1e4, seed=2300, edges=(32, 48, 64))
+    res = {"solves": count, "grid_edges": [32, 48, 64]}
+    for prec, tag in ((F.F32, "fp32_graph"), (F.F64, "fp64_batched")):
+        dt = torch.float32 if prec == F.F32 else torch.float64
+        plans = [F.Plan(r["n"], r["h"], r["bc"], r["layout"], F.CHAT2, prec) for r in reqs]
+        rhs = [W.request_rhs_device(r, dt) for r in reqs]
+        outs = [torch.empty_like(x) for x in rhs]
+        ws = torch.empty(F.batched_workspace_bytes(plans), dtype=torch.uint8, device="cuda")
+        batch = F.Batch(plans, rhs, outs, ws)
+        batch.run()
+        torch.cuda.synchronize()
+        if prec == F.F32:
+            stream = torch.cuda.Stream()
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.stream(stream):
+                with torch.cuda.graph(graph, stream=stream):
+                    batch.run()
+            step = graph.replay
+        else:
+            step = batch.run
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            step()
+        torch.cuda.synchronize()
+        res[tag + "_solves_per_s"] = count * reps / (time.perf_counter() - t0)
+        if prec == F.F64:
+            # plain path: one solve at a time, each waited for
+            for p, x, o in zip(plans, rhs, outs):
+                p.solve(x, o)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for p, x, o in zip(plans, rhs, outs):
+                p.solve(x, o)
+                torch.cuda.synchronize()
+            res["fp64_plain_solves_per_s"] = count / (time.perf_counter() - t0)
+        batch.close()
+        for p in plans:
+            p.close()
+    return res
+
+
+def _percentiles(lat):
+    lat = np.sort(np.asarray(lat))
+    return float(np.percentile(lat, 50) * 1e3), float(np.percentile(lat, 99) * 1e3)
+
+
+def run_serving(count, load=0.7):
+    """The serving stream: mixed grids (edges 32 ... 192), boundary conditions and layouts,
+    FP32 through the serving loop (plans cached on the device), and the same stream on
+    the plain FP64 path (one solve at a time).  Inputs are generated on the device
+    beforehand; latency = completion - arrival on the host clock."""
+    import torch
+    import paper_2211_07777_amd as F
+    from paper_2211_07777_amd import workloads as W
+    reqs = W.serving_stream(count=count, qps=1.0, seed=2211)
+    gaps = np.diff([0.0] + [r["t"] for r in reqs])  # unit-rate arrival gaps
+    rhs32 = [W.request_rhs_device(r, torch.float32) for r in reqs]
+    outs32 = [torch.empty_like(x) for x in rhs32]
+    torch.cuda.synchronize()
+    server = F.Server(workspace_budget_bytes=24 << 30, plan_budget_bytes=64 << 30, slots=8)
+    # cold pass: every plan created (timed separately), results checked below
+    t0 = time.perf_counter()
+    for r, x, o in zip(reqs, rhs32, outs32):
+        server.submit(r["n"], r["h"], r["bc"], r["layout"], x, o)
+    server.wait_all()
+    server.progress()
+    cold_s = time.perf_counter() - t0
+    st_cold = server.stats()
+    # saturated: the whole stream submitted at once, warm plans
+    t0 = time.perf_counter()
+    for r, x, o in zip(reqs, rhs32, outs32):
+        server.submit(r["n"], r["h"], r["bc"], r["layout"], x, o)
+    server.wait_all()
+    server.progress()
+    sat = count / (time.perf_counter() - t0)
+    # open loop at `load` x the saturated rate
+    lam = load * sat
+    arrive = np.cumsum(gaps) / lam
+    lat, done_at, ticket_of = [], {}, {}
+    t_start = time.perf_counter()
+    i = 0
+    while len(done_at) < count:
+        now = time.perf_counter() - t_start
+        while i < count and arrive[i] <= now:
+            r = reqs[i]
+            ticket_of[server.submit(r["n"], r["h"], r["bc"], r["layout"], rhs32[i], outs32[i])] = i
+            i += 1
+        for t in server.progress():
+            done_at[ticket_of[t]] = time.perf_counter() - t_start
+    lat = [done_at[k] - arrive[k] for k in range(count)]
+    p50, p99 = _percentiles(lat)
+    st = server.stats()
+    server.close()
+    # plain FP64 path on the same arrivals: one solve at a time, plans created beforehand
+    plans64 = [F.Plan(r["n"], r["h"], r["bc"], r["layout"], F.CHAT2, F.F64) for r in reqs]
+    rhs64 = [x.double() for x in rhs32]
+    outs64 = [torch.empty_like(x) for x in rhs64]
+    for p, x, o in zip(plans64, rhs64, outs64):
+        p.solve(x, o)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    lat64 = []
+    for k, (p, x, o) in enumerate(zip(plans64, rhs64, outs64)):
+        while time.perf_counter() - t_start < arrive[k]:
+            pass
+        p.solve(x, o)
+        torch.cuda.synchronize()
+        lat64.append(time.perf_counter() - t_start - arrive[k])
+    t64 = time.perf_counter() - t_start
+    p50_64, p99_64 = _percentiles(lat64)
+    err = max(float((a.double() - b).abs().max() / b.abs().max()) for a, b in zip(outs32, outs64))
+    for p in plans64:
+        p.close()
+    return {"requests": count, "grid_edges": [32, 48, 64, 96, 128, 192], "slots": 8,
+            "fp32_saturated_solves_per_s": sat, "arrival_rate_per_s": lam,
+            "fp32_p50_ms": p50, "fp32_p99_ms": p99,
+            "fp64_plain_solves_per_s": count / t64, "fp64_plain_p50_ms": p50_64, "fp64_plain_p99_ms": p99_64,
+            "peak_inflight": st["peak_inflight"], "cold_plan_creation_ms_mean": 1e3 * cold_s / count,
+            "cached_plans": st_cold["cached_plans"], "max_rel_linf_fp32_vs_fp64": err}
+
+
 def oracle_baseline(name, f64, budget_s=15.0):
     """The FP64 oracle on the host cores: whole solves of the same workload, repeated
     until about budget_s seconds of CPU work have been spent."""
@@ -148,6 +277,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="mixed_node_128x128x256", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
+    ap.add_argument("--serving-requests", type=int, default=500,
+                    help="requests of the serving stream (0: skip the serving measurement)")
+    ap.add_argument("--batched-solves", type=int, default=64,
+                    help="small solves of the batched measurement (0: skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -178,6 +311,8 @@ def main():
 
     if args.calib_copy_mib:
         calibration_copy(args.calib_copy_mib)
+    batched = run_batched(args.batched_solves, 20) if args.batched_solves else None
+    serving = run_serving(args.serving_requests) if args.serving_requests else None
 
     mpts32 = user_pts * ncomp / (r32["ms_step"] * 1e-3) / 1e6
     mpts64 = user_pts * ncomp / (r64["ms_step"] * 1e-3) / 1e6
@@ -215,6 +350,8 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic},
         "cpu_baseline": cpu,
+        "batched": batched,
+        "serving": serving,
     }
     print(json.dumps(line))
 

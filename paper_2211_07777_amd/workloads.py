@@ -39,11 +39,10 @@ def gaussian_blob(N=32, lo=-1.0, hi=1.0, sigma=0.1):
     return np.exp(-r2 / (2 * sigma ** 2)), h
 
 
-def gaussian_bumps(coords, L, seed=DEFAULT_SEED, count=8):
-    """coords = (x, y, z) 1-D point arrays, L = (Lx, Ly, Lz); returns f[z, y, x]."""
+def _bump_profiles(coords, L, seed, count):
+    """The seeded bumps as (amplitude, gz, gy, gx) 1-D profiles."""
     rng = np.random.default_rng(seed)
     x, y, z = coords
-    f = np.zeros((len(z), len(y), len(x)))
     for _ in range(count):
         sigma = rng.uniform(0.05, 0.15)
         amp = rng.normal()
@@ -51,8 +50,28 @@ def gaussian_bumps(coords, L, seed=DEFAULT_SEED, count=8):
         gx = np.exp(-((x - c[0]) ** 2) / (2 * sigma ** 2))
         gy = np.exp(-((y - c[1]) ** 2) / (2 * sigma ** 2))
         gz = np.exp(-((z - c[2]) ** 2) / (2 * sigma ** 2))
+        yield amp, gz, gy, gx
+
+
+def gaussian_bumps(coords, L, seed=DEFAULT_SEED, count=8):
+    """coords = (x, y, z) 1-D point arrays, L = (Lx, Ly, Lz); returns f[z, y, x]."""
+    x, y, z = coords
+    f = np.zeros((len(z), len(y), len(x)))
+    for amp, gz, gy, gx in _bump_profiles(coords, L, seed, count):
         f += amp * gz[:, None, None] * gy[None, :, None] * gx[None, None, :]
     return f
+
+
+def gaussian_bumps_device(coords, L, seed=DEFAULT_SEED, count=8, dtype=None):
+    """gaussian_bumps evaluated with torch on the current GPU (same draws, FP64, then cast
+    to dtype): for workloads too large to generate on the host."""
+    import torch
+    x, y, z = coords
+    f = torch.zeros((len(z), len(y), len(x)), dtype=torch.float64, device="cuda")
+    for amp, gz, gy, gx in _bump_profiles(coords, L, seed, count):
+        tz, ty, tx = (torch.from_numpy(v).cuda() for v in (gz, gy, gx))
+        f += amp * tz[:, None, None] * ty[None, :, None] * tx[None, None, :]
+    return f if dtype is None else f.to(dtype)
 
 
 def _ring_vorticity(out, x, centre, normal, R, a, gamma, zpert=None, cutoff=6.0):
@@ -164,8 +183,7 @@ def serving_stream(count=2000, qps=1000.0, seed=DEFAULT_SEED, h=1.0 / 64, edges=
     return reqs
 
 
-def request_rhs(req):
-    """The seeded Gaussian-bump right-hand side of one serving request, f[z, y, x]."""
+def _request_grid(req):
     n, h, layout = req["n"], req["h"], req["layout"]
     coords = []
     for a in range(3):
@@ -173,8 +191,19 @@ def request_rhs(req):
             coords.append(np.arange(n[a] + 1) * h[a])
         else:
             coords.append((np.arange(n[a]) + 0.5) * h[a])
-    L = [n[a] * h[a] for a in range(3)]
+    return coords, [n[a] * h[a] for a in range(3)]
+
+
+def request_rhs(req):
+    """The seeded Gaussian-bump right-hand side of one serving request, f[z, y, x]."""
+    coords, L = _request_grid(req)
     return gaussian_bumps(coords, L, seed=req["seed"])
+
+
+def request_rhs_device(req, dtype=None):
+    """request_rhs generated on the current GPU."""
+    coords, L = _request_grid(req)
+    return gaussian_bumps_device(coords, L, seed=req["seed"], dtype=dtype)
 
 
 def random_field(shape, seed):

@@ -97,3 +97,24 @@ def test_server_evicts_plans_beyond_its_budget():
         assert torch.equal(p.solve(x), o)
         p.close()
     server.close()
+
+
+def test_serving_distribution_sample_matches_oracle():
+    """Requests drawn from the full serving distribution (edges 32 ... 192, every class,
+    both layouts), FP32 through the server, against the FP64 oracle."""
+    import torch
+    reqs = W.serving_stream(count=10, qps=1e4, seed=33)
+    server = F.Server(workspace_budget_bytes=2 << 30, plan_budget_bytes=1 << 30, slots=4)
+    work = []
+    for r in reqs:
+        x = W.request_rhs_device(r, torch.float32)
+        o = torch.empty_like(x)
+        server.submit(r["n"], r["h"], r["bc"], r["layout"], x, o)
+        work.append((r, o))
+    server.wait_all()
+    server.close()
+    for r, o in work:
+        ref = oracle_solve(W.request_rhs(r), r["n"], r["h"], r["bc"], r["layout"])
+        err = rel_linf(o.double().cpu().numpy(), ref)
+        print("request", r["n"], r["bc"], r["layout"], f"rel_linf={err:.2e}")
+        assert err < TOL32, (r, err)
