@@ -1066,6 +1066,27 @@ __device__ __forceinline__ void run_tile(const PassDesc& d, const void* in, void
   else run_tile_e<T, MC, T, 1>(d, in, out, tile, smem);
 }
 
+// XCD-aware order of the tiles.  Workgroups are dispatched to the 8 XCDs round-robin
+// (block b on XCD b mod 8), and each XCD has its own L2.  The tiles are cut into 8
+// contiguous ranges, one per XCD, and the blocks of an XCD walk their range side by side:
+// tiles that are neighbours along the tile axis (and share cache lines of a strided
+// input or output) run at the same time on the same L2.  Tile k of block b (k = 0, 1,
+// ...) is returned, or -1 past the end of the block's share.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_tile(int b, int grid, int k, int tiles) {
+  if (grid < kXcds) {  // too few blocks to give every XCD a share: plain striding
+    const int t = b + k * grid;
+    return t < tiles ? t : -1;
+  }
+  const int x = b % kXcds, j = b / kXcds;
+  const int per = (tiles + kXcds - 1) / kXcds;       // tiles of one XCD
+  const int nbx = (grid - x + kXcds - 1) / kXcds;    // blocks on XCD x
+  const int local = j + k * nbx;
+  if (local >= per) return -1;
+  const int t = x * per + local;
+  return t < tiles ? t : -1;
+}
+
 // Persistent loop over the tiles of a pass: while tile t is transformed in LDS, the
 // input of the next tile of this workgroup (and its Green rows) is already on its way
 // into registers.  The twiddle tables are copied to LDS once, so that the transform
@@ -1079,9 +1100,9 @@ __device__ __forceinline__ void run_pipelined(const PassDesc& d, const void* in,
   constexpr int U = StageCount<T, E, NCL, MC>::U;
   constexpr bool FUSED = fused_of(KIND);
   constexpr int UG = green_stage<T, MC, KIND>();
-  int tile = blockIdx.x;
-  const int stride = gridDim.x;
-  if (tile >= d.tiles) return;
+  int k = 0;
+  int tile = xcd_tile(blockIdx.x, gridDim.x, k, d.tiles);
+  if (tile < 0) return;
   // twiddle tables -> LDS (visible to the transform after the loop's barriers)
   cpx<T>* lt = reinterpret_cast<cpx<T>*>(smem + d.tab_off);
   {
@@ -1106,15 +1127,15 @@ __device__ __forceinline__ void run_pipelined(const PassDesc& d, const void* in,
     commit<U, NCL, E>(v, d, ti, smem);
     if constexpr (FUSED) commit_green<T, UG>(gs, d, ti, smem);
     __syncthreads();
-    const int next = tile + stride;
+    const int next = xcd_tile(blockIdx.x, gridDim.x, ++k, d.tiles);
     TileIdx tn = ti;
-    if (next < d.tiles) {
+    if (next >= 0) {
       tn = tile_index(d, next);
       fetch<U, NCL, false, E>(v, d, in, tn);
       if constexpr (FUSED) fetch_green<T, UG>(gs, d, tn);
     }
     compute<T, MC, KIND>(d, out, ti, smem, tb);
-    if (next >= d.tiles) break;
+    if (next < 0) break;
     tile = next;
     ti = tn;
   }
@@ -1125,20 +1146,26 @@ __device__ __forceinline__ void run_pipelined(const PassDesc& d, const void* in,
 template <typename T, int MC, int KIND>
 __device__ __forceinline__ void run_single(const PassDesc& d, const void* in, void* out,
                                            char* smem) {
-  if ((int)blockIdx.x >= d.tiles) return;
+  // tiles in the XCD-aware order; with a grid of one block per tile each block takes
+  // one or two tiles
   using E = typename std::conditional<in_cplx_of(KIND), cpx<T>, T>::type;
   constexpr int NCL = KIND == K_F_CURL ? 3 : 1;
   constexpr int U = StageCount<T, E, NCL, MC>::U;
   constexpr int UG = green_stage<T, MC, KIND>();
-  RegStage<T, E, U * NCL> v;
-  GreenStage<T, UG> gs;
-  const TileIdx ti = tile_index(d, blockIdx.x);
-  fetch<U, NCL, (MC <= 1), E>(v, d, in, ti);
-  if constexpr (fused_of(KIND)) fetch_green<T, UG>(gs, d, ti);
-  commit<U, NCL, E>(v, d, ti, smem);
-  if constexpr (fused_of(KIND)) commit_green<T, UG>(gs, d, ti, smem);
-  __syncthreads();
-  compute<T, MC, KIND>(d, out, ti, smem, global_tabs<T>(d));
+  for (int k = 0;; ++k) {
+    const int tile = xcd_tile(blockIdx.x, gridDim.x, k, d.tiles);
+    if (tile < 0) return;
+    if (k > 0) __syncthreads();  // the previous tile's LDS reads are finished
+    RegStage<T, E, U * NCL> v;
+    GreenStage<T, UG> gs;
+    const TileIdx ti = tile_index(d, tile);
+    fetch<U, NCL, (MC <= 1), E>(v, d, in, ti);
+    if constexpr (fused_of(KIND)) fetch_green<T, UG>(gs, d, ti);
+    commit<U, NCL, E>(v, d, ti, smem);
+    if constexpr (fused_of(KIND)) commit_green<T, UG>(gs, d, ti, smem);
+    __syncthreads();
+    compute<T, MC, KIND>(d, out, ti, smem, global_tabs<T>(d));
+  }
 }
 
 // The descriptor lives in device memory (uniform loads); the buffers of this solve are

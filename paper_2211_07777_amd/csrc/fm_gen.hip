@@ -171,7 +171,7 @@ hipError_t launch_pass(const PassDesc& d, const PassDesc* dev, const void* in, v
   if (d.tiles <= 0) return hipSuccess;
   if (d.stw == nullptr) {
     if constexpr (sizeof(T) == 8)
-      if (d.M > kMaxFastLen64) return launch_len<T, kRtLong>(d, dev, in, out, st);
+      if (d.M > kMaxFastLen64 || d.long_rt) return launch_len<T, kRtLong>(d, dev, in, out, st);
     return launch_len<T, kRtShort>(d, dev, in, out, st);
   }
 #define FM_CALL(TT, M) launch_len<TT, M>(d, dev, in, out, st)

@@ -195,6 +195,8 @@ struct PassDesc {
   // with the tile's input and keep them in LDS at g_off.  The transform itself then
   // reads no global memory, so the prefetch of the next tile overlaps it.
   int32_t tab_off, stw_n, tw_n;
+  int32_t long_rt;          // FP64: run in the runtime-length class with 16 values per
+                            // thread (a tile that does not fit 8, e.g. a 3-component curl)
   int32_t g_off;
   uint64_t mag_gline;       // division by g.F_line
 };

@@ -312,12 +312,15 @@ TileLds tile_lds(const fm::PassDesc& d, int B, size_t elem, int comps, bool fuse
   return t;
 }
 
+// Kernel length class that fixes the values per thread of a pass.
+int pass_class(const fm::PassDesc& d) { return d.long_rt ? fm::kRtLong : d.M; }
+
 // Twiddle entries the persistent kernel of this pass copies to LDS: the stage table,
 // and for real-to-real gathers the first 2M entries of the 4M table (pre- and
 // post-twiddles).
 void set_lds_tables(fm::PassDesc* d, size_t elem) {
   d->stw_n = d->tw_n = 0;
-  if (!fm::is_fast_len(d->M) || !fm::pipelined_kernel((int)elem, d->M)) return;
+  if (d->long_rt || !fm::is_fast_len(d->M) || !fm::pipelined_kernel((int)elem, d->M)) return;
   d->stw_n = fm::stage_table_size(d->M, fm::max_radix((int)elem));
   if (d->gather == fm::G_R2R) d->tw_n = 2 * d->M;
 }
@@ -332,13 +335,14 @@ int choose_tile(fm::PassDesc* d, size_t elem, int comps, bool fused_r2r, int nb,
     TileLds best_lds{};
     for (int B = 1; B <= bmax; ++B) {
       const int F = comps * ((B + packs - 1) / packs);
-      if ((int64_t)F * d->M > (int64_t)fm::kThreads * fm::elems_per_thread((int)elem, d->M)) break;
+      const int cls = pass_class(*d);
+      if ((int64_t)F * d->M > (int64_t)fm::kThreads * fm::elems_per_thread((int)elem, cls)) break;
       // the register stage must hold the whole input tile (a Hermitian half-spectrum
       // pair has M + 2 values per FFT line), and a fused tile's Green rows
-      if ((int64_t)B * d->in_n > (int64_t)fm::kThreads * fm::stage_values((int)elem, d->M, d->in_cplx != 0, comps))
+      if ((int64_t)B * d->in_n > (int64_t)fm::kThreads * fm::stage_values((int)elem, cls, d->in_cplx != 0, comps))
         break;
       if (d->fused && (int64_t)B * d->g.F_line >
-                          (int64_t)fm::kThreads * fm::green_values((int)elem, d->M, packs == 2))
+                          (int64_t)fm::kThreads * fm::green_values((int)elem, cls, packs == 2))
         break;
       const TileLds t = tile_lds(*d, B, elem, comps, fused_r2r);
       if (t.total > (size_t)cap) break;
@@ -423,7 +427,7 @@ int make_tables_and_green(fm_plan_s* p, hipStream_t st) {
   // per-stage tables of the lengths with compile-time kernels
   for (int i = 0; i < 5; ++i) {
     const int M = p->pass[i].M;
-    if (!fm::is_fast_len(M)) continue;
+    if (!fm::is_fast_len(M) || p->pass[i].long_rt) continue;
     if (tile_in_span_bytes(p->pass[i], p->elem) >= (int64_t(1) << 32)) continue;
     if (!p->stw.count(M)) {
       void* ptr = nullptr;
@@ -623,8 +627,10 @@ bool pass_in_bounds(const fm::PassDesc& d, int64_t in_size, int64_t out_size, si
   const int comps = (d.fused && d.g.curl) ? 3 : 1;
   const int packs = (d.gather == fm::G_CPLX) ? 1 : 2;
   const int F = comps * ((d.B + packs - 1) / packs);
-  if ((int64_t)F * M > (int64_t)fm::kThreads * fm::elems_per_thread((int)elem, M)) return false;
-  if ((int64_t)d.B * d.in_n > (int64_t)fm::kThreads * fm::stage_values((int)elem, M, d.in_cplx != 0, comps))
+  const int cls = pass_class(d);
+  if (d.long_rt && elem != 8) return false;
+  if ((int64_t)F * M > (int64_t)fm::kThreads * fm::elems_per_thread((int)elem, cls)) return false;
+  if ((int64_t)d.B * d.in_n > (int64_t)fm::kThreads * fm::stage_values((int)elem, cls, d.in_cplx != 0, comps))
     return false;
   const size_t fft = (size_t)F * (M + 1) * 2 * elem;
   const size_t raw = (size_t)comps * d.B * (d.in_n + 1) * (d.in_cplx ? 2 : 1) * elem;
@@ -639,7 +645,7 @@ bool pass_in_bounds(const fm::PassDesc& d, int64_t in_size, int64_t out_size, si
   // the staged regions follow the tile, in order, inside lds_bytes
   size_t end = need;
   if (d.fused) {
-    if ((int64_t)d.B * d.g.F_line > (int64_t)fm::kThreads * fm::green_values((int)elem, M, packs == 2))
+    if ((int64_t)d.B * d.g.F_line > (int64_t)fm::kThreads * fm::green_values((int)elem, cls, packs == 2))
       return false;
     if ((size_t)d.g_off < end || d.g_off % 16) return false;
     end = d.g_off + (size_t)d.B * d.g.F_line * elem;
@@ -854,7 +860,13 @@ int build_plan(fm_plan_s* p) {
     if (rc) return rc;
     const bool fused_curl = (i == 2) && curl;
     d.ncomp = p->ncomp;
-    const int rc2 = choose_tile(&d, p->elem, fused_curl ? 3 : 1, (i == 2) && d.gather == fm::G_R2R, d.nb);
+    d.long_rt = 0;
+    int rc2 = choose_tile(&d, p->elem, fused_curl ? 3 : 1, (i == 2) && d.gather == fm::G_R2R, d.nb);
+    if (rc2 && p->prec == FM_F64) {
+      // no tile fits 8 FP64 values per thread: the runtime-length class with 16
+      d.long_rt = 1;
+      rc2 = choose_tile(&d, p->elem, fused_curl ? 3 : 1, (i == 2) && d.gather == fm::G_R2R, d.nb);
+    }
     if (rc2) return rc2;
     d.tiles = ((d.nb + d.B - 1) / d.B) * d.nc * (fused_curl ? 1 : p->ncomp);
     set_magics(&d);
@@ -983,7 +995,7 @@ int build_batch(int count, const fm_plan* plans, const void* const* rhs_dev, voi
     std::map<int, std::vector<int>> by_class;
     for (int i = 0; i < count; ++i) {
       const fm::PassDesc& d = all[5 * (size_t)i + ps];
-      const int rt = (d.M > fm::kMaxFastLen64) ? fm::kRtLong : fm::kRtShort;
+      const int rt = (d.M > fm::kMaxFastLen64 || d.long_rt) ? fm::kRtLong : fm::kRtShort;
       by_class[d.stw ? d.M : rt].push_back(i);
     }
     for (auto& kv : by_class) {

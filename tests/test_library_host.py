@@ -92,3 +92,12 @@ def test_tile_input_fits_register_stage(prec, values):
         for layout in (0, 1):
             F.plan_inspect([m, 8, 6], [0.1] * 3, [[2, 2], [0, 1], [3, 3]], layout, F.CHAT2, prec)
             F.plan_inspect([6, m, 8], [0.1] * 3, [[3, 3], [2, 2], [3, 3]], layout, F.CHAT2, prec)
+
+
+def test_biot_savart_512_plans_in_both_precisions():
+    # three components of a 1024-point line do not fit 8 FP64 values per thread: the
+    # fused pass falls back to the 16-value kernel class instead of failing
+    for prec in (F.F32, F.F64):
+        info = F.plan_inspect([512] * 3, [2 / 512] * 3, [[3, 3]] * 3, 0, F.CHAT2, prec, F.BIOT_SAVART, 3)
+        assert info["fft_len"] == [1024] * 3
+        assert 1 <= info["lines_per_tile"][2] <= 64
