@@ -63,6 +63,7 @@ def lib():
         L.oracle_solve.argtypes = [ip, dp, ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp]
         L.oracle_green_spectrum.argtypes = [ip, dp, ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
         L.oracle_spectral_dims.argtypes = [ip, dp, ip, ctypes.c_int, ip]
+        L.oracle_direct_points.argtypes = [ip, dp, ip, ctypes.c_int, ctypes.c_int, dp, ctypes.c_int, ip, dp]
         L.oracle_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -143,6 +144,19 @@ def solve(rhs, n, h, bc, layout, green=0, kind=0, mode=FAST):
     out = np.empty_like(rhs)
     _check(lib().oracle_solve(_ip(n), _dp(h), _ip(bc), layout, green, kind, mode, _dp(rhs), _dp(out)))
     return out if kind == 1 else out[0]
+
+
+def direct_points(rhs, n, h, bc, layout, points, green=0):
+    """u at the given user points [(ix, iy, iz), ...] by the direct convolution sum
+    (Poisson; every axis fully or semi-unbounded).  rhs: [nz, ny, nx] FP64."""
+    n, h, bc = _prep(n, h, bc)
+    shp = user_shape(n, layout)
+    rhs = np.ascontiguousarray(rhs, dtype=np.float64).reshape(shp)
+    pts = np.ascontiguousarray(np.asarray(points, dtype=np.int32).reshape(-1, 3))
+    out = np.empty(len(pts))
+    _check(lib().oracle_direct_points(_ip(n), _dp(h), _ip(bc), layout, green, _dp(rhs), len(pts),
+                                      pts.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dp(out)))
+    return out
 
 
 def spectral_dims(n, h, bc, layout):

@@ -792,6 +792,73 @@ int solve_direct(const Problem& P, const double* rhs, double* out) {
   return 0;
 }
 
+// The plain definition at chosen points, for problems whose three axes are all
+// convolution directions (fully or semi-unbounded, Sec. II-C): the discrete convolution
+// of the image-extended right-hand side with the sampled kernel, times the cell volume.
+// pts holds (x, y, z) user indices.  Costs one sum over the whole grid per point.
+int direct_points(const Problem& P, const double* rhs, int npts, const int* pts, double* out) {
+  if (P.kind != 0) return -3;
+  for (int ax = 0; ax < 3; ++ax)
+    if (!P.ax[ax].unb) return -3;
+  const Dims du = user_dims(P);
+  struct Src { int j; double x; double sign; };
+  std::vector<Src> src[3];
+  double cellvol = 1.0;
+  for (int ax = 0; ax < 3; ++ax) {
+    const Axis& A = P.ax[ax];
+    cellvol *= A.h;
+    const double off = A.node ? 0.0 : 0.5;
+    if (A.cls == C_UU) {
+      for (int j = 0; j < A.nuser; ++j) src[ax].push_back({j, (j + off) * A.h, 1.0});
+      continue;
+    }
+    const double sgn = (A.cls == C_EU || A.cls == C_UE) ? 1.0 : -1.0;
+    const double face = A.rev ? A.L() : 0.0;
+    for (int j = 0; j < A.nuser; ++j) {
+      const double x = (j + off) * A.h;
+      const double xi = 2.0 * face - x;
+      if (A.node && std::fabs(xi - x) < 0.25 * A.h) {
+        if (sgn > 0) src[ax].push_back({j, x, 1.0});
+        continue;
+      }
+      src[ax].push_back({j, x, 1.0});
+      src[ax].push_back({j, xi, sgn});
+    }
+  }
+  const long nx = du.n[0], ny = du.n[1];
+  for (int q = 0; q < npts; ++q) {
+    const int* ip = pts + 3 * q;
+    double xt[3];
+    bool zero = false;
+    for (int ax = 0; ax < 3; ++ax) {
+      const Axis& A = P.ax[ax];
+      if (ip[ax] < 0 || ip[ax] >= A.nuser) return -2;
+      xt[ax] = (ip[ax] + (A.node ? 0.0 : 0.5)) * A.h;
+      if (A.node && ((A.cls == C_OU && ip[ax] == 0) || (A.cls == C_UO && ip[ax] == A.N))) zero = true;
+    }
+    double acc = 0.0;
+    const long s2n = (long)src[2].size();
+#pragma omp parallel for reduction(+ : acc) schedule(static)
+    for (long s2 = 0; s2 < s2n; ++s2) {
+      const Src& Z = src[2][s2];
+      const double dz = xt[2] - Z.x;
+      double part = 0.0;
+      for (const Src& Y : src[1]) {
+        const double dy = xt[1] - Y.x;
+        const double* row = rhs + nx * (Y.j + ny * (long)Z.j);
+        const double syz = Y.sign * Z.sign;
+        for (const Src& X : src[0]) {
+          const double dx = xt[0] - X.x;
+          part += syz * X.sign * P.g.value(std::sqrt(dx * dx + dy * dy + dz * dz), 0.0) * row[X.j];
+        }
+      }
+      acc += part;
+    }
+    out[q] = zero ? 0.0 : acc * cellvol;
+  }
+  return 0;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------------
@@ -855,6 +922,16 @@ int oracle_solve(const int* n, const double* h, const int* bc, int layout, int g
   if (rc) return rc;
   if (mode == MODE_DIRECT) return solve_direct(P, rhs, out);
   return solve_spectral(P, rhs, out, mode == MODE_NAIVE ? MODE_NAIVE : MODE_FAST);
+}
+
+// The solution at npts user points (x, y, z indices in pts[3 * npts]) by the direct
+// convolution sum; every axis must be fully or semi-unbounded; Poisson only.
+int oracle_direct_points(const int* n, const double* h, const int* bc, int layout, int green,
+                         const double* rhs, int npts, const int* pts, double* out) {
+  Problem P;
+  const int rc = make_problem(n, h, bc, layout, green, 0, &P);
+  if (rc) return rc;
+  return direct_points(P, rhs, npts, pts, out);
 }
 
 // Green's spectrum on the (unfolded) spectral grid, complex interleaved, [z][y][x].

@@ -319,3 +319,26 @@ def test_axis_permutation_equivariance():
     n2, h2, bc2 = [n[2], n[1], n[0]], [h[2], h[1], h[0]], [bc[2], bc[1], bc[0]]
     u2 = O.solve(np.ascontiguousarray(np.transpose(f, (2, 1, 0))), n2, h2, bc2, O.NODE)
     assert np.abs(np.transpose(u2, (2, 1, 0)) - u).max() < 1e-14 * np.abs(u).max()
+
+
+@pytest.mark.parametrize("layout", [0, 1])
+def test_direct_points_equal_the_full_solves(layout):
+    """Sampled direct sums (used at sizes where the full oracle is too slow) agree with the
+    full direct and FFT forms on every combination of unbounded and semi-unbounded axes."""
+    rng = np.random.default_rng(50 + layout)
+    U = [(3, 3), (0, 3), (1, 3), (3, 0), (3, 1)]
+    for trial in range(12):
+        bc = [list(U[rng.integers(len(U))]) for _ in range(3)]
+        n = [int(v) for v in rng.choice([3, 4, 5, 6, 7], size=3)]
+        h = [float(v) for v in rng.uniform(0.05, 0.2, size=3)]
+        shp = O.user_shape(n, layout)
+        f = rng.standard_normal(shp)
+        full = O.solve(f, n, h, bc, layout, mode=O.DIRECT)
+        fast = O.solve(f, n, h, bc, layout)
+        pts = [(int(rng.integers(shp[2])), int(rng.integers(shp[1])), int(rng.integers(shp[0]))) for _ in range(6)]
+        pts += [(0, 0, 0), (shp[2] - 1, shp[1] - 1, shp[0] - 1)]
+        got = O.direct_points(f, n, h, bc, layout, pts)
+        scale = np.abs(full).max()
+        for (ix, iy, iz), v in zip(pts, got):
+            assert abs(v - full[iz, iy, ix]) <= 1e-13 * scale, (bc, n, (ix, iy, iz))
+            assert abs(v - fast[iz, iy, ix]) <= 1e-12 * scale, (bc, n, (ix, iy, iz))
