@@ -65,13 +65,14 @@ def make_input(name):
     raise KeyError(name)
 
 
-def run_gpu(name, f64, prec, steps, warmup):
+def run_gpu(name, f64, prec, steps, warmup, tune=True):
     import torch
     import paper_2211_07777_amd as F
     w = WORKLOADS[name]
     ncomp = 3 if w["kind"] == 1 else 1
     plan = F.Plan(w["n"], w["h"], w["bc"], w["layout"], F.CHAT2, prec, w["kind"], ncomp)
     info = F.plan_inspect(w["n"], w["h"], w["bc"], w["layout"], F.CHAT2, prec, w["kind"], ncomp)
+    tiling = plan.tune() if tune else plan.tiling()
     rhs = torch.from_numpy(f64).to(device="cuda", dtype=plan.dtype).reshape(plan.shape).contiguous()
     out = torch.empty_like(rhs)
     ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
@@ -97,7 +98,8 @@ def run_gpu(name, f64, prec, steps, warmup):
     torch.cuda.synchronize()
     pass_ms = np.array([[evs[k][p].elapsed_time(evs[k][p + 1]) for p in range(5)] for k in range(steps)])
     plan.close()
-    return dict(ms_step=ms_step, pass_ms=pass_ms.mean(axis=0).tolist(), info=info, result=result)
+    return dict(ms_step=ms_step, pass_ms=pass_ms.mean(axis=0).tolist(), info=info, result=result,
+                tiling=tiling)
 
 
 def calibration_copy(mib):
@@ -277,6 +279,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="mixed_node_128x128x256", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
+    ap.add_argument("--no-tune", action="store_true", help="time the planner's tiling, not the tuned one")
     ap.add_argument("--serving-requests", type=int, default=500,
                     help="requests of the serving stream (0: skip the serving measurement)")
     ap.add_argument("--batched-solves", type=int, default=64,
@@ -295,8 +298,8 @@ def main():
     f64 = make_input(name)
     ncomp = 3 if w["kind"] == 1 else 1
     user_pts = float(np.prod([n + (1 if w["layout"] == 1 else 0) for n in w["n"]]))
-    r32 = run_gpu(name, f64, F.F32, args.steps, args.warmup)
-    r64 = run_gpu(name, f64, F.F64, args.steps, args.warmup)
+    r32 = run_gpu(name, f64, F.F32, args.steps, args.warmup, not args.no_tune)
+    r64 = run_gpu(name, f64, F.F64, args.steps, args.warmup, not args.no_tune)
 
     cpu = None
     err32 = err64 = None
@@ -343,6 +346,8 @@ def main():
                  "rel_linf_vs_oracle": err64},
         "fp32_rel_linf_vs_oracle": err32,
         "pass_ms_fp32": r32["pass_ms"],
+        "tiling_fp32": r32["tiling"],
+        "tuned": not args.no_tune,
         "pass_ms_fp64": r64["pass_ms"],
         "effective_GBps_fp32": step_bytes / (sum(r32["pass_ms"]) * 1e-3) / 1e9,
         "roofline": {"bound": "hbm", "kernel": f"pass {dom + 1} ({kinds[dom]}, pass_kernel<float>)",

@@ -219,6 +219,9 @@ __device__ __forceinline__ const __attribute__((address_space(1))) T* gptr(const
   return (const __attribute__((address_space(1))) T*)(p);
 }
 
+// Position of FFT slot i in an LDS line (see fft_line_stride).
+__device__ __forceinline__ int pad16(int i) { return i + (i >> 4); }
+
 // Per-element loops over a tile take kChunk elements per thread at a time, so that
 // their LDS reads are issued together.
 constexpr int kChunk = 1;
@@ -298,9 +301,10 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, int ls, int F, int M, int
       SmallDft<R, S, T>::run(v[i]);
       const int t = tt[i];
       const int k = t % Ns;
-      const int base = lin[i] * ls + (t - k) * R + k;
+      const int base = (t - k) * R + k;
+      cpx<T>* row = buf + lin[i] * ls;
 #pragma unroll
-      for (int q = 0; q < R; ++q) buf[base + q * Ns] = v[i][q];
+      for (int q = 0; q < R; ++q) row[pad16(base + q * Ns)] = v[i][q];
     }
   }
   __syncthreads();
@@ -345,9 +349,10 @@ __device__ __forceinline__ void fft_stage_ct(cpx<T>* buf, int ls, int F,
       SmallDft<R, S, T>::run(v[i]);
       const int t = tt[i];
       const int k = t % Ns;
-      const int base = lin[i] * ls + (t - k) * R + k;
+      const int base = (t - k) * R + k;
+      cpx<T>* row = buf + lin[i] * ls;
 #pragma unroll
-      for (int q = 0; q < R; ++q) buf[base + q * Ns] = v[i][q];
+      for (int q = 0; q < R; ++q) row[pad16(base + q * Ns)] = v[i][q];
     }
   }
   __syncthreads();
@@ -359,7 +364,7 @@ __device__ __forceinline__ void stages_ct(cpx<T>* buf, int ls, int F, const cpx<
   constexpr int R = radix_at(M, s, Prec<T>::RMAX);
   if constexpr (R != 0) {
     fft_stage_ct<T, M, R, Ns, S>(buf, ls, F, stw + stage_table_offset(M, s, Prec<T>::RMAX), load);
-    auto lds = [buf, ls](int line, int idx) { return buf[line * ls + idx]; };
+    auto lds = [buf, ls](int line, int idx) { return buf[line * ls + pad16(idx)]; };
     stages_ct<T, M, S, s + 1, Ns * R>(buf, ls, F, stw, lds);
   }
 }
@@ -387,7 +392,7 @@ __device__ __forceinline__ void fft_lines(cpx<T>* buf, int ls, int F, const Pass
   } else {
     constexpr int EL = elems_per_thread((int)sizeof(T), MC);
     const cpx<T>* tw = reinterpret_cast<const cpx<T>*>(d.tw);
-    auto lds = [buf, ls](int line, int idx) { return buf[line * ls + idx]; };
+    auto lds = [buf, ls](int line, int idx) { return buf[line * ls + pad16(idx)]; };
     int Ns = 1;
     for (int s = 0; s < d.nstages; ++s) {
       const int R = d.radix[s];
@@ -510,7 +515,7 @@ __device__ __forceinline__ void extend_r2r(cpx<T>* buf, int ls, int F, int M, co
       const int e = e0 + u * kThreads;
       if (e < total) {
         const int f = e / M, m = e - f * M;
-        buf[f * ls + m] = z[u];
+        buf[f * ls + pad16(m)] = z[u];
       }
     }
   }
@@ -526,7 +531,7 @@ __device__ __forceinline__ T scatter_r2r(const cpx<T>* buf, int ls, const R2R& r
   const int q = r.out_rev ? r.out_base - j : j + r.out_base;
   const bool ok = q >= r.qlo && q <= r.qhi;   // outside: the coefficient is 0
   const int qc = ok ? q : r.qlo;
-  cpx<T> Y = buf[(l >> 1) * ls + qc];
+  cpx<T> Y = buf[(l >> 1) * ls + pad16(qc)];
   if (r.a2) Y = cmul(Y, tw[2 * qc + r.b2]);  // exp(-i pi a (q + b) / nh), a = 1/2
   const T v = r.sin ? ((l & 1) ? Y.x : -Y.y) : ((l & 1) ? Y.y : Y.x);
   return ok ? v : T(0);
@@ -647,7 +652,7 @@ __device__ void plain_compute(const PassDesc& d, void* out, const TileIdx& ti, c
   const int nl = ti.nl;
   const cpx<T>* tw = tb.tw;
   const int M = MC > 1 ? MC : d.M;
-  const int ls = M + 1;
+  const int ls = fft_line_stride(M);
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem);
   const int64_t out_off = ti.comp * d.out_s_comp + ti.c * d.out_s_c + ti.b0 * d.out_s_b;
   const int rs = d.in_n + 1;
@@ -667,19 +672,19 @@ __device__ void plain_compute(const PassDesc& d, void* out, const TileIdx& ti, c
   } else {
     GatherR2R<T> g{reinterpret_cast<const T*>(smem + d.raw_off), rs, d.in_n, nl, d.r2r, tw};
     extend_r2r<T, MC>(buf, ls, F, M, g);
-    auto lds = [buf, ls](int line, int idx) { return buf[line * ls + idx]; };
+    auto lds = [buf, ls](int line, int idx) { return buf[line * ls + pad16(idx)]; };
     fft_lines<T, MC, -1>(buf, ls, F, d, tb.stw, lds);
   }
 
   // 3) write the lines into the output layout
   if (scatter == S_CPLX) {
-    auto val = [&](int l, int j) { return buf[l * ls + (j < M ? j : j - M)]; };
+    auto val = [&](int l, int j) { return buf[l * ls + pad16(j < M ? j : j - M)]; };
     store_tile<false>(reinterpret_cast<cpx<T>*>(out) + out_off, d.out_s_line, d.out_s_b, d.out_s_c,
                       nl, d.out_n, d.mag_out, d.B, d.mag_B, ti.b0, ti.c, d.fix, val);
   } else if (scatter == S_R2C2) {
     auto val = [&](int l, int k) {
       const cpx<T>* z = buf + (l >> 1) * ls;
-      const cpx<T> zk = z[k], zm = z[k == 0 ? 0 : M - k];
+      const cpx<T> zk = z[pad16(k)], zm = z[pad16(k == 0 ? 0 : M - k)];
       if (l & 1) return cpx<T>{T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x)};
       return cpx<T>{T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
     };
@@ -687,7 +692,7 @@ __device__ void plain_compute(const PassDesc& d, void* out, const TileIdx& ti, c
                       nl, d.out_n, d.mag_out, d.B, d.mag_B, ti.b0, ti.c, d.fix, val);
   } else if (scatter == S_REAL2) {
     auto val = [&](int l, int j) {
-      const cpx<T> z = buf[(l >> 1) * ls + (j < M ? j : j - M)];
+      const cpx<T> z = buf[(l >> 1) * ls + pad16(j < M ? j : j - M)];
       return (l & 1) ? z.y : z.x;
     };
     if (d.has_fix) store_real<T, MC, true>(d, out, ti, out_off, val);
@@ -710,7 +715,7 @@ __device__ void fused_compute(const PassDesc& d, void* out, const TileIdx& ti, c
   const int nl = ti.nl, b0 = ti.b0, c = ti.c, comp = ti.comp;  // curl: comp = 0
   const cpx<T>* tw = tb.tw;
   const int M = MC > 1 ? MC : d.M;
-  const int ls = M + 1;
+  const int ls = fft_line_stride(M);
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem);
   const int rs = d.in_n + 1;
   const int ncl = curl ? 3 : 1;   // components held by the tile
@@ -722,7 +727,7 @@ __device__ void fused_compute(const PassDesc& d, void* out, const TileIdx& ti, c
   if (gather == G_R2R) {
     // ---- all-real-to-real problem: forward R2R -> spectrum in LDS -> inverse R2R
     const int F = (nl + 1) / 2;
-    auto lds = [buf, ls](int line, int idx) { return buf[line * ls + idx]; };
+    auto lds = [buf, ls](int line, int idx) { return buf[line * ls + pad16(idx)]; };
     {
       GatherR2R<T> g{reinterpret_cast<const T*>(smem + d.raw_off), rs, d.in_n, nl, d.r2r, tw};
       extend_r2r<T, MC>(buf, ls, F, M, g);
@@ -777,7 +782,7 @@ __device__ void fused_compute(const PassDesc& d, void* out, const TileIdx& ti, c
           const T g0 = gl[l0 * FL + kk];
           const T g1 = gl[l1 * FL + kk];
           const int km = (k == 0) ? 0 : M - k;
-          const cpx<T> zk = buf[f * ls + k], zm = buf[f * ls + km];
+          const cpx<T> zk = buf[f * ls + pad16(k)], zm = buf[f * ls + pad16(km)];
           const cpx<T> x1 = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
           const cpx<T> x2 = {T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x)};
           // Z'_k = g0 X1 + i g1 X2 ;  Z'_{M-k} = g0 conj(X1) + i g1 conj(X2)
@@ -787,15 +792,15 @@ __device__ void fused_compute(const PassDesc& d, void* out, const TileIdx& ti, c
         [&](int e, const Pair& v) {
           const int f = e / H, k = e - f * H;
           const int km = (k == 0) ? 0 : M - k;
-          buf[f * ls + k] = v.a;
-          if (km != k) buf[f * ls + km] = v.b;
+          buf[f * ls + pad16(k)] = v.a;
+          if (km != k) buf[f * ls + pad16(km)] = v.b;
         });
     __syncthreads();
-    auto lds = [buf, ls](int line, int idx) { return buf[line * ls + idx]; };
+    auto lds = [buf, ls](int line, int idx) { return buf[line * ls + pad16(idx)]; };
     fft_lines<T, MC, +1>(buf, ls, F, d, tb.stw, lds);
     const int64_t out_off = comp * d.out_s_comp + c * d.out_s_c + b0 * d.out_s_b;
     auto val = [&](int l, int j) {
-      const cpx<T> z = buf[(l >> 1) * ls + (j < M ? j : j - M)];
+      const cpx<T> z = buf[(l >> 1) * ls + pad16(j < M ? j : j - M)];
       return (l & 1) ? z.y : z.x;
     };
     store_tile<false>(reinterpret_cast<T*>(out) + out_off, d.out_s_line, d.out_s_b, d.out_s_c, nl,
@@ -815,12 +820,12 @@ __device__ void fused_compute(const PassDesc& d, void* out, const TileIdx& ti, c
         [&](int e) {
           const int l = e / M, k = e - l * M;
           const T g = gl[l * FL + fold_index(k, d.g.fold_line)];
-          const cpx<T> z = buf[l * ls + k];
+          const cpx<T> z = buf[l * ls + pad16(k)];
           return cpx<T>{z.x * g, z.y * g};
         },
         [&](int e, const cpx<T>& v) {
           const int l = e / M, k = e - l * M;
-          buf[l * ls + k] = v;
+          buf[l * ls + pad16(k)] = v;
         });
   } else {
     const T wc = signed_wave<T>(c, d.g.M_c, T(d.g.dw_c));
@@ -838,9 +843,9 @@ __device__ void fused_compute(const PassDesc& d, void* out, const TileIdx& ti, c
           const T wx = d.g.axis_line == 0 ? wl : (d.g.axis_b == 0 ? wb : wc);
           const T wy = d.g.axis_line == 1 ? wl : (d.g.axis_b == 1 ? wb : wc);
           const T wz = d.g.axis_line == 2 ? wl : (d.g.axis_b == 2 ? wb : wc);
-          const cpx<T> fx = buf[(0 * nl + l) * ls + k];
-          const cpx<T> fy = buf[(1 * nl + l) * ls + k];
-          const cpx<T> fz = buf[(2 * nl + l) * ls + k];
+          const cpx<T> fx = buf[(0 * nl + l) * ls + pad16(k)];
+          const cpx<T> fy = buf[(1 * nl + l) * ls + pad16(k)];
+          const cpx<T> fz = buf[(2 * nl + l) * ls + pad16(k)];
           // u_hat = G * i (w x f_hat)
           const cpx<T> cx = {wy * fz.x - wz * fy.x, wy * fz.y - wz * fy.y};
           const cpx<T> cy = {wz * fx.x - wx * fz.x, wz * fx.y - wx * fz.y};
@@ -849,21 +854,21 @@ __device__ void fused_compute(const PassDesc& d, void* out, const TileIdx& ti, c
         },
         [&](int e, const Tri& v) {
           const int l = e / M, k = e - l * M;
-          buf[(0 * nl + l) * ls + k] = v.x;
-          buf[(1 * nl + l) * ls + k] = v.y;
-          buf[(2 * nl + l) * ls + k] = v.z;
+          buf[(0 * nl + l) * ls + pad16(k)] = v.x;
+          buf[(1 * nl + l) * ls + pad16(k)] = v.y;
+          buf[(2 * nl + l) * ls + pad16(k)] = v.z;
         });
   }
   __syncthreads();
   {
-    auto lds = [buf, ls](int line, int idx) { return buf[line * ls + idx]; };
+    auto lds = [buf, ls](int line, int idx) { return buf[line * ls + pad16(idx)]; };
     fft_lines<T, MC, +1>(buf, ls, F, d, tb.stw, lds);
   }
   for (int q = 0; q < ncl; ++q) {
     const int cc = curl ? q : comp;
     const int64_t out_off = cc * d.out_s_comp + c * d.out_s_c + b0 * d.out_s_b;
     const cpx<T>* z = buf + (size_t)q * nl * ls;
-    auto val = [&](int l, int j) { return z[l * ls + (j < M ? j : j - M)]; };
+    auto val = [&](int l, int j) { return z[l * ls + pad16(j < M ? j : j - M)]; };
     store_tile<false>(reinterpret_cast<cpx<T>*>(out) + out_off, d.out_s_line, d.out_s_b, d.out_s_c,
                       nl, d.out_n, d.mag_out, d.B, d.mag_B, b0, c, nofix, val);
   }

@@ -130,6 +130,11 @@ constexpr int radix_at(int M, int s, int rmax) {
   }
 }
 
+// LDS layout of an FFT line: slot i sits at i + i / 16 (one unused slot after every
+// 16), so that the power-of-two strides of the radix passes' writes fall on different
+// LDS banks; lines are fft_line_stride(M) slots apart.
+constexpr int fft_line_stride(int M) { return M + (M >> 4) + 1; }
+
 // Lengths with compile-time kernels (other lengths use the runtime-length kernel).
 constexpr int kFastLens[] = {32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 2048, 4096};
 

@@ -288,7 +288,7 @@ TileLds tile_lds(const fm::PassDesc& d, int B, size_t elem, int comps, bool fuse
   const size_t cplx = 2 * elem;
   const size_t in_elem = d.in_cplx ? cplx : elem;
   const int F = comps * ((B + packs - 1) / packs);
-  const size_t fft = (size_t)F * (d.M + 1) * cplx;
+  const size_t fft = (size_t)F * fm::fft_line_stride(d.M) * cplx;
   const size_t raw = (size_t)comps * B * (d.in_n + 1) * in_elem;
   TileLds t{};
   size_t end;
@@ -632,7 +632,7 @@ bool pass_in_bounds(const fm::PassDesc& d, int64_t in_size, int64_t out_size, si
   if ((int64_t)F * M > (int64_t)fm::kThreads * fm::elems_per_thread((int)elem, cls)) return false;
   if ((int64_t)d.B * d.in_n > (int64_t)fm::kThreads * fm::stage_values((int)elem, cls, d.in_cplx != 0, comps))
     return false;
-  const size_t fft = (size_t)F * (M + 1) * 2 * elem;
+  const size_t fft = (size_t)F * fm::fft_line_stride(M) * 2 * elem;
   const size_t raw = (size_t)comps * d.B * (d.in_n + 1) * (d.in_cplx ? 2 : 1) * elem;
   size_t need = std::max(fft, raw);
   if (d.gather == fm::G_R2R) {
