@@ -346,6 +346,7 @@ def main():
                  "rel_linf_vs_oracle": err64},
         "fp32_rel_linf_vs_oracle": err32,
         "pass_ms_fp32": r32["pass_ms"],
+        "algo_bytes_fp32": r32["info"]["algo_bytes"],
         "tiling_fp32": r32["tiling"],
         "tuned": not args.no_tune,
         "pass_ms_fp64": r64["pass_ms"],
