@@ -127,7 +127,8 @@ int fm_solve_batched(int count, const fm_plan* plans, const void* const* rhs_dev
                      void* hip_stream);
 
 /* Autotuner: times every pass of the plan on the device for candidate tilings (lines
- * per tile and a persistent or one-tile-per-workgroup grid), keeps the fastest valid one
+ * per tile; a persistent grid, or one tile per workgroup with the twiddle tables in LDS
+ * or read from global memory), keeps the fastest valid one
  * per pass in the plan, and uses it for every later solve.  Results can change at the
  * rounding level only: two real lines share one complex FFT, and which lines are paired
  * follows the tiling.  workspace_dev as for fm_solve (NULL: the plan's own);
@@ -139,7 +140,9 @@ int fm_plan_tune(fm_plan p, void* workspace_dev, void* hip_stream);
  * not counting its own workspace. */
 int fm_plan_device_bytes(fm_plan p, size_t* bytes);
 
-/* The plan's current tiling per pass: lines per tile, tiles, persistent grid (1/0). */
+/* The plan's current tiling per pass: lines per tile, tiles, and the launch mode
+ * persist[i]: 1 persistent grid (twiddle tables in LDS), 0 one tile per workgroup with
+ * the tables in LDS, 2 one tile per workgroup with the tables read from global memory. */
 int fm_plan_tiling(fm_plan p, int lines_per_tile[5], int tiles[5], int persist[5]);
 
 /* A batch prepared once and launched many times: the same work as fm_solve_batched on

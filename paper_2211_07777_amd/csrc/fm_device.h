@@ -219,6 +219,16 @@ __device__ __forceinline__ const __attribute__((address_space(1))) T* gptr(const
   return (const __attribute__((address_space(1))) T*)(p);
 }
 
+// Twiddle tables are read through a pointer of type P: a generic pointer into LDS (the
+// tables the persistent kernels stage) or a global-memory pointer (GTab).  Keeping the
+// address space in the type makes the global reads plain global loads.
+template <typename T>
+using GTab = const __attribute__((address_space(1))) cpx<T>*;
+template <typename T, class P>
+__device__ __forceinline__ cpx<T> twid(P p, int i) {
+  return cpx<T>{p[i].x, p[i].y};
+}
+
 // Position of FFT slot i in an LDS line (see fft_line_stride).
 __device__ __forceinline__ int pad16(int i) { return i + (i >> 4); }
 
@@ -262,9 +272,9 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t n, uint64_t mag) {
 // 4M table; compile-time form: M, R, Ns are constants and twiddles come from the
 // per-stage table (contiguous per butterfly).
 // ---------------------------------------------------------------------------------
-template <typename T, int EL, int R, int S, class Load>
-__device__ __forceinline__ void fft_stage(cpx<T>* buf, int ls, int F, int M, int Ns,
-                                          const cpx<T>* __restrict__ tw, Load& load) {
+template <typename T, int EL, int R, int S, class P, class Load>
+__device__ __forceinline__ void fft_stage(cpx<T>* buf, int ls, int F, int M, int Ns, P tw,
+                                          Load& load) {
   constexpr int NB = (EL + R - 1) / R;
   cpx<T> v[NB][R];
   int lin[NB], tt[NB];
@@ -286,7 +296,7 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, int ls, int F, int M, int
       for (int r = 0; r < R; ++r) {
         cpx<T> a = load(line, t + r * MR);
         if (r > 0 && k > 0) {
-          cpx<T> w = tw[k * r * twstep];
+          cpx<T> w = twid<T>(tw, k * r * twstep);
           if (S > 0) w.y = -w.y;
           a = cmul(a, w);
         }
@@ -310,9 +320,8 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, int ls, int F, int M, int
   __syncthreads();
 }
 
-template <typename T, int M, int R, int Ns, int S, class Load>
-__device__ __forceinline__ void fft_stage_ct(cpx<T>* buf, int ls, int F,
-                                             const cpx<T>* __restrict__ stw, Load& load) {
+template <typename T, int M, int R, int Ns, int S, class P, class Load>
+__device__ __forceinline__ void fft_stage_ct(cpx<T>* buf, int ls, int F, P stw, Load& load) {
   constexpr int NB = (elems_per_thread((int)sizeof(T), M) + R - 1) / R;
   constexpr int MR = M / R;
   cpx<T> v[NB][R];
@@ -332,10 +341,10 @@ __device__ __forceinline__ void fft_stage_ct(cpx<T>* buf, int ls, int F,
       for (int r = 0; r < R; ++r) v[i][r] = load(line, t + r * MR);
       if (Ns > 1) {
         const int k = t % Ns;
-        const cpx<T>* w = stw + k * (R - 1);
+        const P w = stw + k * (R - 1);
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          cpx<T> ww = w[r - 1];
+          cpx<T> ww = twid<T>(w, r - 1);
           if (S > 0) ww.y = -ww.y;
           v[i][r] = cmul(v[i][r], ww);
         }
@@ -358,9 +367,8 @@ __device__ __forceinline__ void fft_stage_ct(cpx<T>* buf, int ls, int F,
   __syncthreads();
 }
 
-template <typename T, int M, int S, int s, int Ns, class Load>
-__device__ __forceinline__ void stages_ct(cpx<T>* buf, int ls, int F, const cpx<T>* stw,
-                                          Load& load) {
+template <typename T, int M, int S, int s, int Ns, class P, class Load>
+__device__ __forceinline__ void stages_ct(cpx<T>* buf, int ls, int F, P stw, Load& load) {
   constexpr int R = radix_at(M, s, Prec<T>::RMAX);
   if constexpr (R != 0) {
     fft_stage_ct<T, M, R, Ns, S>(buf, ls, F, stw + stage_table_offset(M, s, Prec<T>::RMAX), load);
@@ -369,9 +377,9 @@ __device__ __forceinline__ void stages_ct(cpx<T>* buf, int ls, int F, const cpx<
   }
 }
 
-template <typename T, int EL, int S, class Load>
+template <typename T, int EL, int S, class P, class Load>
 __device__ __forceinline__ void fft_stage_dispatch(int R, cpx<T>* buf, int ls, int F, int M,
-                                                   int Ns, const cpx<T>* tw, Load& load) {
+                                                   int Ns, P tw, Load& load) {
   switch (R) {
     case 8: fft_stage<T, EL, 8, S>(buf, ls, F, M, Ns, tw, load); break;
     case 4: fft_stage<T, EL, 4, S>(buf, ls, F, M, Ns, tw, load); break;
@@ -384,14 +392,14 @@ __device__ __forceinline__ void fft_stage_dispatch(int R, cpx<T>* buf, int ls, i
 }
 
 // Full FFT of F lines; result in buf in natural order.  MC = compile-time length or 0.
-template <typename T, int MC, int S, class Load>
-__device__ __forceinline__ void fft_lines(cpx<T>* buf, int ls, int F, const PassDesc& d,
-                                          const cpx<T>* stw, Load& load0) {
+template <typename T, int MC, int S, class P, class Load>
+__device__ __forceinline__ void fft_lines(cpx<T>* buf, int ls, int F, const PassDesc& d, P stw,
+                                          Load& load0) {
   if constexpr (MC > 1) {
     stages_ct<T, MC, S, 0, 1>(buf, ls, F, stw, load0);
   } else {
     constexpr int EL = elems_per_thread((int)sizeof(T), MC);
-    const cpx<T>* tw = reinterpret_cast<const cpx<T>*>(d.tw);
+    const GTab<T> tw = gptr<cpx<T>>(d.tw);  // runtime lengths: the 4M table in global memory
     auto lds = [buf, ls](int line, int idx) { return buf[line * ls + pad16(idx)]; };
     int Ns = 1;
     for (int s = 0; s < d.nstages; ++s) {
@@ -405,10 +413,10 @@ __device__ __forceinline__ void fft_lines(cpx<T>* buf, int ls, int F, const Pass
 
 // Twiddle tables seen by a tile: in LDS for persistent kernels (copied once per
 // workgroup), else in global memory.
-template <typename T>
+template <class P>
 struct Tabs {
-  const cpx<T>* stw;  // stage twiddles of the compile-time length
-  const cpx<T>* tw;   // 4M table (persistent real-to-real kernels: its first 2M entries)
+  P stw;  // stage twiddles of the compile-time length
+  P tw;   // 4M table (persistent real-to-real kernels: its first 2M entries)
 };
 
 // ---------------------------------------------------------------------------------
@@ -455,12 +463,12 @@ struct GatherHerm2 {  // two Hermitian half-spectra -> one full spectrum
   }
 };
 
-template <typename T>
+template <typename T, class P>
 struct GatherR2R {  // symmetric extension of two real lines, with pre-twiddle
   const T* raw;
   int rs, in_n, nl;
   R2R r;
-  const cpx<T>* tw;  // 4M table
+  P tw;  // 4M table
   // Branch-free: the mirrored source index and its weight are selected per lane, the
   // index is clamped into the line, and a sample outside the data gets weight 0.
   __device__ cpx<T> operator()(int f, int m) const {
@@ -490,15 +498,15 @@ struct GatherR2R {  // symmetric extension of two real lines, with pre-twiddle
     const T a = raw[l * rs + jc];
     const T b = raw[(two ? l + 1 : l) * rs + jc];
     cpx<T> z = {c * a, two ? c * b : T(0)};
-    if (r.b2) z = cmul(z, tw[2 * m]);  // exp(-i pi m b / nh), b = 1/2
+    if (r.b2) z = cmul(z, twid<T>(tw, 2 * m));  // exp(-i pi m b / nh), b = 1/2
     return z;
   }
 };
 
 // Write the symmetric extensions of a real-to-real tile into the FFT buffer (one LDS
 // pass; the raw tile lives outside the buffer), so that the FFT stages read plain LDS.
-template <typename T, int MC>
-__device__ __forceinline__ void extend_r2r(cpx<T>* buf, int ls, int F, int M, const GatherR2R<T>& g) {
+template <typename T, int MC, class G>
+__device__ __forceinline__ void extend_r2r(cpx<T>* buf, int ls, int F, int M, const G& g) {
   const int total = F * M;
   for (int e0 = threadIdx.x; e0 < total; e0 += kChunk * kThreads) {
     cpx<T> z[kChunk];
@@ -525,14 +533,14 @@ __device__ __forceinline__ void extend_r2r(cpx<T>* buf, int ls, int F, int M, co
 // ---------------------------------------------------------------------------------
 // Scatters: value of output element j of tile line l, from the FFT buffer.
 // ---------------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ T scatter_r2r(const cpx<T>* buf, int ls, const R2R& r,
-                                         const cpx<T>* tw, int l, int j) {
+template <typename T, class P>
+__device__ __forceinline__ T scatter_r2r(const cpx<T>* buf, int ls, const R2R& r, P tw, int l,
+                                         int j) {
   const int q = r.out_rev ? r.out_base - j : j + r.out_base;
   const bool ok = q >= r.qlo && q <= r.qhi;   // outside: the coefficient is 0
   const int qc = ok ? q : r.qlo;
   cpx<T> Y = buf[(l >> 1) * ls + pad16(qc)];
-  if (r.a2) Y = cmul(Y, tw[2 * qc + r.b2]);  // exp(-i pi a (q + b) / nh), a = 1/2
+  if (r.a2) Y = cmul(Y, twid<T>(tw, 2 * qc + r.b2));  // exp(-i pi a (q + b) / nh), a = 1/2
   const T v = r.sin ? ((l & 1) ? Y.x : -Y.y) : ((l & 1) ? Y.y : Y.x);
   return ok ? v : T(0);
 }
@@ -643,14 +651,14 @@ __device__ __forceinline__ void store_real(const PassDesc& d, void* out, const T
                   d.out_n, d.mag_out, d.B, d.mag_B, ti.b0, ti.c, d.fix, val);
 }
 
-template <typename T, int MC, int KIND>
+template <typename T, int MC, int KIND, class P>
 __device__ void plain_compute(const PassDesc& d, void* out, const TileIdx& ti, char* smem,
-                              const Tabs<T>& tb) {
+                              const Tabs<P>& tb) {
   const int gather = KIND == K_ANY ? d.gather : gather_of(KIND);
   const int scatter = KIND == K_ANY ? d.scatter : scatter_of(KIND);
   const int sign = KIND == K_ANY ? d.sign : (KIND == K_C2C_I || KIND == K_C2R ? +1 : -1);
   const int nl = ti.nl;
-  const cpx<T>* tw = tb.tw;
+  const P tw = tb.tw;
   const int M = MC > 1 ? MC : d.M;
   const int ls = fft_line_stride(M);
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem);
@@ -670,7 +678,7 @@ __device__ void plain_compute(const PassDesc& d, void* out, const TileIdx& ti, c
     GatherHerm2<T> g{reinterpret_cast<const cpx<T>*>(smem), rs, M, nl};
     fft_lines<T, MC, +1>(buf, ls, F, d, tb.stw, g);
   } else {
-    GatherR2R<T> g{reinterpret_cast<const T*>(smem + d.raw_off), rs, d.in_n, nl, d.r2r, tw};
+    GatherR2R<T, P> g{reinterpret_cast<const T*>(smem + d.raw_off), rs, d.in_n, nl, d.r2r, tw};
     extend_r2r<T, MC>(buf, ls, F, M, g);
     auto lds = [buf, ls](int line, int idx) { return buf[line * ls + pad16(idx)]; };
     fft_lines<T, MC, -1>(buf, ls, F, d, tb.stw, lds);
@@ -707,13 +715,13 @@ __device__ void plain_compute(const PassDesc& d, void* out, const TileIdx& ti, c
 // ---------------------------------------------------------------------------------
 // Fused pass 3 on one tile: forward FFT, spectral multiply, inverse FFT.
 // ---------------------------------------------------------------------------------
-template <typename T, int MC, int KIND>
+template <typename T, int MC, int KIND, class P>
 __device__ void fused_compute(const PassDesc& d, void* out, const TileIdx& ti, char* smem,
-                              const Tabs<T>& tb) {
+                              const Tabs<P>& tb) {
   const int gather = KIND == K_ANY ? d.gather : gather_of(KIND);
   const bool curl = KIND == K_ANY ? (d.g.curl != 0) : (KIND == K_F_CURL);
   const int nl = ti.nl, b0 = ti.b0, c = ti.c, comp = ti.comp;  // curl: comp = 0
-  const cpx<T>* tw = tb.tw;
+  const P tw = tb.tw;
   const int M = MC > 1 ? MC : d.M;
   const int ls = fft_line_stride(M);
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem);
@@ -729,7 +737,7 @@ __device__ void fused_compute(const PassDesc& d, void* out, const TileIdx& ti, c
     const int F = (nl + 1) / 2;
     auto lds = [buf, ls](int line, int idx) { return buf[line * ls + pad16(idx)]; };
     {
-      GatherR2R<T> g{reinterpret_cast<const T*>(smem + d.raw_off), rs, d.in_n, nl, d.r2r, tw};
+      GatherR2R<T, P> g{reinterpret_cast<const T*>(smem + d.raw_off), rs, d.in_n, nl, d.r2r, tw};
       extend_r2r<T, MC>(buf, ls, F, M, g);
       fft_lines<T, MC, -1>(buf, ls, F, d, tb.stw, lds);
     }
@@ -749,7 +757,7 @@ __device__ void fused_compute(const PassDesc& d, void* out, const TileIdx& ti, c
         });
     __syncthreads();
     {
-      GatherR2R<T> g{spec, ss, d.spec_n, nl, d.r2r2, tw};
+      GatherR2R<T, P> g{spec, ss, d.spec_n, nl, d.r2r2, tw};
       extend_r2r<T, MC>(buf, ls, F, M, g);
       fft_lines<T, MC, -1>(buf, ls, F, d, tb.stw, lds);
     }
@@ -815,18 +823,14 @@ __device__ void fused_compute(const PassDesc& d, void* out, const TileIdx& ti, c
     fft_lines<T, MC, -1>(buf, ls, F, d, tb.stw, g);
   }
   if (!curl) {
-    chunked<cpx<T>>(
-        nl * M,
-        [&](int e) {
-          const int l = e / M, k = e - l * M;
-          const T g = gl[l * FL + fold_index(k, d.g.fold_line)];
-          const cpx<T> z = buf[l * ls + pad16(k)];
-          return cpx<T>{z.x * g, z.y * g};
-        },
-        [&](int e, const cpx<T>& v) {
-          const int l = e / M, k = e - l * M;
-          buf[l * ls + pad16(k)] = v;
-        });
+    // the multiplication by the Green's spectrum is the first inverse stage's load
+    const int fl = d.g.fold_line;
+    auto lds_g = [buf, ls, gl, FL, fl](int line, int idx) {
+      const cpx<T> z = buf[line * ls + pad16(idx)];
+      const T g = gl[line * FL + fold_index(idx, fl)];
+      return cpx<T>{z.x * g, z.y * g};
+    };
+    fft_lines<T, MC, +1>(buf, ls, F, d, tb.stw, lds_g);
   } else {
     const T wc = signed_wave<T>(c, d.g.M_c, T(d.g.dw_c));
     const T dwl = T(d.g.dw_line), dwb = T(d.g.dw_b);
@@ -858,9 +862,7 @@ __device__ void fused_compute(const PassDesc& d, void* out, const TileIdx& ti, c
           buf[(1 * nl + l) * ls + pad16(k)] = v.y;
           buf[(2 * nl + l) * ls + pad16(k)] = v.z;
         });
-  }
-  __syncthreads();
-  {
+    __syncthreads();
     auto lds = [buf, ls](int line, int idx) { return buf[line * ls + pad16(idx)]; };
     fft_lines<T, MC, +1>(buf, ls, F, d, tb.stw, lds);
   }
@@ -1029,13 +1031,13 @@ constexpr int green_stage() {
 }
 
 template <typename T>
-__device__ __forceinline__ Tabs<T> global_tabs(const PassDesc& d) {
-  return {reinterpret_cast<const cpx<T>*>(d.stw), reinterpret_cast<const cpx<T>*>(d.tw)};
+__device__ __forceinline__ Tabs<GTab<T>> global_tabs(const PassDesc& d) {
+  return {gptr<cpx<T>>(d.stw), gptr<cpx<T>>(d.tw)};
 }
 
-template <typename T, int MC, int KIND>
+template <typename T, int MC, int KIND, class P>
 __device__ __forceinline__ void compute(const PassDesc& d, void* out, const TileIdx& ti,
-                                        char* smem, const Tabs<T>& tb) {
+                                        char* smem, const Tabs<P>& tb) {
   if constexpr (KIND == K_ANY) {
     if (d.fused) fused_compute<T, MC, K_ANY>(d, out, ti, smem, tb);
     else plain_compute<T, MC, K_ANY>(d, out, ti, smem, tb);
@@ -1121,7 +1123,7 @@ __device__ __forceinline__ void run_pipelined(const PassDesc& d, const void* in,
   }
   // real-to-real kinds always have their twiddles staged (tw_n = 2M); other kinds do
   // not read tw in the compile-time kernels
-  const Tabs<T> tb{lt, lt + d.stw_n};
+  const Tabs<const cpx<T>*> tb{lt, lt + d.stw_n};
   RegStage<T, E, U * NCL> v;
   GreenStage<T, UG> gs;
   TileIdx ti = tile_index(d, tile);
@@ -1146,8 +1148,9 @@ __device__ __forceinline__ void run_pipelined(const PassDesc& d, const void* in,
   }
 }
 
-// Runtime lengths and long FP64 lines: one tile per workgroup, no register prefetch,
-// tables read from global memory.
+// One tile per workgroup (runtime lengths, long FP64 lines, and compile-time lengths
+// launched with one workgroup per tile): no register prefetch, tables read from global
+// memory.
 template <typename T, int MC, int KIND>
 __device__ __forceinline__ void run_single(const PassDesc& d, const void* in, void* out,
                                            char* smem) {
@@ -1175,12 +1178,15 @@ __device__ __forceinline__ void run_single(const PassDesc& d, const void* in, vo
 
 // The descriptor lives in device memory (uniform loads); the buffers of this solve are
 // kernel arguments.
-template <typename T, int MC, int KIND>
+// PIPE = 1: the persistent pipelined loop (compile-time lengths that allow it, and a
+// descriptor with persist = 1); PIPE = 0: one tile per workgroup with the twiddle tables
+// read from global memory, which leaves LDS for more workgroups per CU.
+template <typename T, int MC, int KIND, int PIPE>
 __global__ __launch_bounds__(kThreads) void pass_kernel(const PassDesc* __restrict__ dp,
                                                         const void* in, void* out) {
   extern __shared__ __align__(16) char smem[];
-  if constexpr (!pipelined_kernel((int)sizeof(T), MC)) run_single<T, MC, KIND>(*dp, in, out, smem);
-  else run_pipelined<T, MC, KIND>(*dp, in, out, smem);
+  if constexpr (PIPE && pipelined_kernel((int)sizeof(T), MC)) run_pipelined<T, MC, KIND>(*dp, in, out, smem);
+  else run_single<T, MC, KIND>(*dp, in, out, smem);
 }
 
 // Batched form: tiles of many descriptors of one length class in one launch;

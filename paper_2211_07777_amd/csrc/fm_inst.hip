@@ -26,38 +26,45 @@ static hipError_t allow_full_lds() {
 template <int KIND>
 static hipError_t launch_kind(const PassDesc& d, const PassDesc* dev, const void* in, void* out,
                               hipStream_t st) {
-  if (d.lds_bytes > kSoftLds) {
-    const hipError_t e = allow_full_lds<&pass_kernel<FM_T, FM_MC, KIND>>();
-    if (e != hipSuccess) return e;
-  }
-  // persistent workgroups: as many as can be resident at once (each loops over tiles);
-  // the other kernels take one tile per workgroup
-  if (!pipelined_kernel((int)sizeof(FM_T), FM_MC)) {
-    hipLaunchKernelGGL((pass_kernel<FM_T, FM_MC, KIND>), dim3(d.tiles), dim3(kThreads), d.lds_bytes,
-                       st, dev, in, out);
-    return hipGetLastError();
-  }
-  static int resident[kMaxLds / 256 + 1] = {0};
-  const int slot = d.lds_bytes / 256;
-  if (resident[slot] == 0) {
-    int per_cu = 0, dev_id = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pass_kernel<FM_T, FM_MC, KIND>,
-                                                      kThreads, d.lds_bytes) != hipSuccess ||
-        per_cu < 1)
-      per_cu = 1;
-    if (hipGetDevice(&dev_id) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id) != hipSuccess ||
-        cus < 1)
-      cus = 256;
-    resident[slot] = per_cu * cus;
-  }
   static const bool persistent = [] {
     const char* e = std::getenv("FLUXMI_PERSISTENT");
     return e == nullptr || std::atoi(e) != 0;
   }();
-  const int grid = (!persistent || !d.persist || d.tiles < resident[slot]) ? d.tiles : resident[slot];
-  hipLaunchKernelGGL((pass_kernel<FM_T, FM_MC, KIND>), dim3(grid), dim3(kThreads), d.lds_bytes, st,
-                     dev, in, out);
+  if constexpr (pipelined_kernel((int)sizeof(FM_T), FM_MC)) {
+    // twiddle tables staged in LDS: the pipelined kernel, on a persistent grid (as many
+    // workgroups as can be resident at once, each looping over tiles) or one tile each
+    if (d.lds_tabs) {
+      if (d.lds_bytes > kSoftLds) {
+        const hipError_t e = allow_full_lds<&pass_kernel<FM_T, FM_MC, KIND, 1>>();
+        if (e != hipSuccess) return e;
+      }
+      static int resident[kMaxLds / 256 + 1] = {0};
+      const int slot = d.lds_bytes / 256;
+      if (resident[slot] == 0) {
+        int per_cu = 0, dev_id = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pass_kernel<FM_T, FM_MC, KIND, 1>,
+                                                          kThreads, d.lds_bytes) != hipSuccess ||
+            per_cu < 1)
+          per_cu = 1;
+        if (hipGetDevice(&dev_id) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id) != hipSuccess ||
+            cus < 1)
+          cus = 256;
+        resident[slot] = per_cu * cus;
+      }
+      const int grid = (!persistent || !d.persist || d.tiles < resident[slot]) ? d.tiles : resident[slot];
+      hipLaunchKernelGGL((pass_kernel<FM_T, FM_MC, KIND, 1>), dim3(grid), dim3(kThreads), d.lds_bytes,
+                         st, dev, in, out);
+      return hipGetLastError();
+    }
+  }
+  // one tile per workgroup, tables read from global memory
+  if (d.lds_bytes > kSoftLds) {
+    const hipError_t e = allow_full_lds<&pass_kernel<FM_T, FM_MC, KIND, 0>>();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((pass_kernel<FM_T, FM_MC, KIND, 0>), dim3(d.tiles), dim3(kThreads), d.lds_bytes,
+                     st, dev, in, out);
   return hipGetLastError();
 }
 

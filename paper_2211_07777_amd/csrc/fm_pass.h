@@ -189,8 +189,8 @@ struct PassDesc {
   // n / d = (n * mag) >> 32 for n * d < 2^32
   uint64_t mag_in, mag_out, mag_B, mag_spec;
   const void* stw;          // stage twiddle table of a compile-time length (or null)
-  int32_t persist;          // compile-time-length kernels: 1 = as many workgroups as fit
-                            // on the device, each looping over tiles; 0 = one tile each
+  int32_t persist;          // with lds_tabs: 1 = as many workgroups as fit on the device,
+                            // each looping over tiles; 0 = one tile each
   int32_t kind;             // PassKind
   int32_t raw_off;          // byte offset of the raw input tile in LDS (0: aliases the
                             // FFT buffer; real-to-real tiles keep it apart)
@@ -204,6 +204,9 @@ struct PassDesc {
                             // thread (a tile that does not fit 8, e.g. a 3-component curl)
   int32_t g_off;
   uint64_t mag_gline;       // division by g.F_line
+  int32_t lds_tabs;         // compile-time-length kernels that allow it: 1 = twiddle tables
+                            // staged in LDS (persistent loop, or one tile per workgroup);
+                            // 0 = one tile per workgroup reading them from global memory
 };
 
 // Sampling description of the Green's function for the spectrum generation (FP64).

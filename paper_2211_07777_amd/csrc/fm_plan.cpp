@@ -317,10 +317,11 @@ int pass_class(const fm::PassDesc& d) { return d.long_rt ? fm::kRtLong : d.M; }
 
 // Twiddle entries the persistent kernel of this pass copies to LDS: the stage table,
 // and for real-to-real gathers the first 2M entries of the 4M table (pre- and
-// post-twiddles).
+// post-twiddles).  Descriptors with lds_tabs = 0 read them from global memory.
 void set_lds_tables(fm::PassDesc* d, size_t elem) {
   d->stw_n = d->tw_n = 0;
-  if (d->long_rt || !fm::is_fast_len(d->M) || !fm::pipelined_kernel((int)elem, d->M)) return;
+  if (!d->lds_tabs || d->long_rt || !fm::is_fast_len(d->M) || !fm::pipelined_kernel((int)elem, d->M))
+    return;
   d->stw_n = fm::stage_table_size(d->M, fm::max_radix((int)elem));
   if (d->gather == fm::G_R2R) d->tw_n = 2 * d->M;
 }
@@ -861,6 +862,8 @@ int build_plan(fm_plan_s* p) {
     const bool fused_curl = (i == 2) && curl;
     d.ncomp = p->ncomp;
     d.long_rt = 0;
+    d.persist = 1;
+    d.lds_tabs = 1;
     int rc2 = choose_tile(&d, p->elem, fused_curl ? 3 : 1, (i == 2) && d.gather == fm::G_R2R, d.nb);
     if (rc2 && p->prec == FM_F64) {
       // no tile fits 8 FP64 values per thread: the runtime-length class with 16
@@ -870,7 +873,6 @@ int build_plan(fm_plan_s* p) {
     if (rc2) return rc2;
     d.tiles = ((d.nb + d.B - 1) / d.B) * d.nc * (fused_curl ? 1 : p->ncomp);
     set_magics(&d);
-    d.persist = 1;
   }
   for (int i = 0; i < 5; ++i) p->pass[i].kind = pass_kind(p->pass[i]);
   const int64_t sizes_in[5] = {p->Vu, p->V1, p->V2, p->V2, p->V1};
@@ -1269,16 +1271,28 @@ int fm_solve_batched(int count, const fm_plan* plans, const void* const* rhs_dev
   return run_batch(b, st);
 }
 
-// A pass re-tiled with at most bmax lines per tile; false if no such tiling is valid
-// for this plan (the persistent kernels address a tile with 32-bit offsets).
-bool retile(const fm_plan_s* p, int i, int bmax, int persist, fm::PassDesc* out) {
+// Launch mode of a descriptor, as fm_plan_tiling reports it: 1 persistent with LDS
+// tables, 0 one tile per workgroup with LDS tables, 2 one tile per workgroup with global
+// tables (the only mode of the runtime-length and long FP64 kernels).
+int launch_mode(const fm::PassDesc& d, size_t elem) {
+  const bool pipelined = !d.long_rt && fm::is_fast_len(d.M) && fm::pipelined_kernel((int)elem, d.M);
+  if (!pipelined || !d.lds_tabs) return 2;
+  return d.persist ? 1 : 0;
+}
+
+// A pass re-tiled with at most bmax lines per tile, in launch mode `mode` (1 persistent
+// with LDS tables, 0 one tile per workgroup with LDS tables, 2 one tile per workgroup
+// with global tables); false if no such tiling is valid for this plan (the
+// compile-time-length kernels address a tile with 32-bit offsets).
+bool retile(const fm_plan_s* p, int i, int bmax, int mode, fm::PassDesc* out) {
   fm::PassDesc d = p->pass[i];
   const bool fused_curl = (i == 2) && p->kind == FM_BIOT_SAVART;
+  d.persist = mode == 1;
+  d.lds_tabs = mode != 2;
   if (choose_tile(&d, p->elem, fused_curl ? 3 : 1, (i == 2) && d.gather == fm::G_R2R, d.nb, bmax))
     return false;
   d.tiles = ((d.nb + d.B - 1) / d.B) * d.nc * (fused_curl ? 1 : p->ncomp);
   set_magics(&d);
-  d.persist = persist;
   if (d.stw && tile_in_span_bytes(d, p->elem) >= (int64_t(1) << 32)) return false;
   const int64_t sizes_in[5] = {p->Vu, p->V1, p->V2, p->V2, p->V1};
   const int64_t sizes_out[5] = {p->V1, p->V2, p->V2, p->V1, p->Vu};
@@ -1336,12 +1350,12 @@ int fm_plan_tune(fm_plan p, void* workspace_dev, void* hip_stream) {
     fm::PassDesc best = p->pass[i];
     float best_ms = 0.f;
     he = time_pass(i, best, &best_ms);
-    std::vector<std::pair<int, int>> seen{{best.B, best.persist}};
+    std::vector<std::pair<int, int>> seen{{best.B, launch_mode(best, p->elem)}};
     for (const int bmax : {64, 32, 16, 8, 4, 2, 1}) {
-      for (const int persist : {1, 0}) {
+      for (const int mode : {1, 0, 2}) {
         fm::PassDesc d;
-        if (he != hipSuccess || !retile(p, i, bmax, persist, &d)) continue;
-        const std::pair<int, int> key{d.B, d.persist};
+        if (he != hipSuccess || !retile(p, i, bmax, mode, &d)) continue;
+        const std::pair<int, int> key{d.B, launch_mode(d, p->elem)};
         if (std::find(seen.begin(), seen.end(), key) != seen.end()) continue;
         seen.push_back(key);
         float ms = 0.f;
@@ -1379,7 +1393,7 @@ int fm_plan_tiling(fm_plan p, int lines_per_tile[5], int tiles[5], int persist[5
   for (int i = 0; i < 5; ++i) {
     lines_per_tile[i] = p->pass[i].B;
     tiles[i] = p->pass[i].tiles;
-    persist[i] = p->pass[i].persist;
+    persist[i] = launch_mode(p->pass[i], p->elem);
   }
   return FM_OK;
 }

@@ -223,7 +223,8 @@ class Plan:
         return self.tiling()
 
     def tiling(self):
-        """(lines per tile, tiles, persistent grid) of the five passes."""
+        """(lines per tile, tiles, launch mode) of the five passes; mode 1 = persistent
+        grid, 0 = one tile per workgroup with LDS tables, 2 = with global tables."""
         b, t, q = (ctypes.c_int * 5)(), (ctypes.c_int * 5)(), (ctypes.c_int * 5)()
         _check(library().fm_plan_tiling(self._h, b, t, q), "fm_plan_tiling")
         return {"lines_per_tile": list(b), "tiles": list(t), "persistent": list(q)}

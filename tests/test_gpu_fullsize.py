@@ -1,4 +1,4 @@
-"""Parity at the benchmark sizes, in the configuration bench.py times.
+"""Parity at the benchmark sizes, in the configuration bench.py times (tuned plans).
 
 * unbounded cell 512^3, scalar Poisson: sampled outputs against the oracle's direct
   convolution sum, point by point;
@@ -21,6 +21,7 @@ def _solve(n, h, bc, layout, kind, f64, prec):
     import torch
     ncomp = 3 if kind == 1 else 1
     plan = F.Plan(n, h, bc, layout, F.CHAT2, prec, kind, ncomp)
+    plan.tune()  # the tiling bench.py times
     x = torch.from_numpy(f64).to("cuda", plan.dtype).reshape(plan.shape).contiguous()
     u = plan.solve(x)
     torch.cuda.synchronize()
