@@ -321,7 +321,8 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, int ls, int F, int M, int
 }
 
 template <typename T, int M, int R, int Ns, int S, class P, class Load>
-__device__ __forceinline__ void fft_stage_ct(cpx<T>* buf, int ls, int F, P stw, Load& load) {
+__device__ __forceinline__ void fft_stage_ct(cpx<T>* buf, int ls, int F, P stw, Load& load,
+                                             int keep) {
   constexpr int NB = (elems_per_thread((int)sizeof(T), M) + R - 1) / R;
   constexpr int MR = M / R;
   cpx<T> v[NB][R];
@@ -361,19 +362,23 @@ __device__ __forceinline__ void fft_stage_ct(cpx<T>* buf, int ls, int F, P stw, 
       const int base = (t - k) * R + k;
       cpx<T>* row = buf + lin[i] * ls;
 #pragma unroll
-      for (int q = 0; q < R; ++q) row[pad16(base + q * Ns)] = v[i][q];
+      for (int q = 0; q < R; ++q) {
+        // the last stage (Ns R = M) writes slot t + q Ns: only the first `keep` are read
+        if (Ns * R < M || base + q * Ns < keep) row[pad16(base + q * Ns)] = v[i][q];
+      }
     }
   }
   __syncthreads();
 }
 
 template <typename T, int M, int S, int s, int Ns, class P, class Load>
-__device__ __forceinline__ void stages_ct(cpx<T>* buf, int ls, int F, P stw, Load& load) {
+__device__ __forceinline__ void stages_ct(cpx<T>* buf, int ls, int F, P stw, Load& load, int keep) {
   constexpr int R = radix_at(M, s, Prec<T>::RMAX);
   if constexpr (R != 0) {
-    fft_stage_ct<T, M, R, Ns, S>(buf, ls, F, stw + stage_table_offset(M, s, Prec<T>::RMAX), load);
+    fft_stage_ct<T, M, R, Ns, S>(buf, ls, F, stw + stage_table_offset(M, s, Prec<T>::RMAX), load,
+                                 keep);
     auto lds = [buf, ls](int line, int idx) { return buf[line * ls + pad16(idx)]; };
-    stages_ct<T, M, S, s + 1, Ns * R>(buf, ls, F, stw, lds);
+    stages_ct<T, M, S, s + 1, Ns * R>(buf, ls, F, stw, lds, keep);
   }
 }
 
@@ -392,11 +397,13 @@ __device__ __forceinline__ void fft_stage_dispatch(int R, cpx<T>* buf, int ls, i
 }
 
 // Full FFT of F lines; result in buf in natural order.  MC = compile-time length or 0.
+// Compile-time lengths write only the first `keep` outputs of each line (the rest are
+// cropped by the caller and never read).
 template <typename T, int MC, int S, class P, class Load>
 __device__ __forceinline__ void fft_lines(cpx<T>* buf, int ls, int F, const PassDesc& d, P stw,
-                                          Load& load0) {
+                                          Load& load0, int keep = 1 << 30) {
   if constexpr (MC > 1) {
-    stages_ct<T, MC, S, 0, 1>(buf, ls, F, stw, load0);
+    stages_ct<T, MC, S, 0, 1>(buf, ls, F, stw, load0, keep);
   } else {
     constexpr int EL = elems_per_thread((int)sizeof(T), MC);
     const GTab<T> tw = gptr<cpx<T>>(d.tw);  // runtime lengths: the 4M table in global memory
@@ -669,14 +676,16 @@ __device__ void plain_compute(const PassDesc& d, void* out, const TileIdx& ti, c
   const int F = (gather == G_CPLX) ? nl : (nl + 1) / 2;
   if (gather == G_CPLX) {
     GatherCplx<T> g{reinterpret_cast<const cpx<T>*>(smem), rs, d.n_data};
-    if (sign < 0) fft_lines<T, MC, -1>(buf, ls, F, d, tb.stw, g);
-    else fft_lines<T, MC, +1>(buf, ls, F, d, tb.stw, g);
+    // complex lines are written from their first out_n slots (cropped inverse)
+    const int keep = scatter == S_CPLX ? min(d.out_n, M) : M;
+    if (sign < 0) fft_lines<T, MC, -1>(buf, ls, F, d, tb.stw, g, keep);
+    else fft_lines<T, MC, +1>(buf, ls, F, d, tb.stw, g, keep);
   } else if (gather == G_REAL2) {
     GatherReal2<T> g{reinterpret_cast<const T*>(smem), rs, d.n_data, nl};
     fft_lines<T, MC, -1>(buf, ls, F, d, tb.stw, g);
   } else if (gather == G_HERM2) {
     GatherHerm2<T> g{reinterpret_cast<const cpx<T>*>(smem), rs, M, nl};
-    fft_lines<T, MC, +1>(buf, ls, F, d, tb.stw, g);
+    fft_lines<T, MC, +1>(buf, ls, F, d, tb.stw, g, scatter == S_REAL2 ? min(d.out_n, M) : M);
   } else {
     GatherR2R<T, P> g{reinterpret_cast<const T*>(smem + d.raw_off), rs, d.in_n, nl, d.r2r, tw};
     extend_r2r<T, MC>(buf, ls, F, M, g);
@@ -830,7 +839,7 @@ __device__ void fused_compute(const PassDesc& d, void* out, const TileIdx& ti, c
       const T g = gl[line * FL + fold_index(idx, fl)];
       return cpx<T>{z.x * g, z.y * g};
     };
-    fft_lines<T, MC, +1>(buf, ls, F, d, tb.stw, lds_g);
+    fft_lines<T, MC, +1>(buf, ls, F, d, tb.stw, lds_g, min(d.out_n, M));
   } else {
     const T wc = signed_wave<T>(c, d.g.M_c, T(d.g.dw_c));
     const T dwl = T(d.g.dw_line), dwb = T(d.g.dw_b);
@@ -864,7 +873,7 @@ __device__ void fused_compute(const PassDesc& d, void* out, const TileIdx& ti, c
         });
     __syncthreads();
     auto lds = [buf, ls](int line, int idx) { return buf[line * ls + pad16(idx)]; };
-    fft_lines<T, MC, +1>(buf, ls, F, d, tb.stw, lds);
+    fft_lines<T, MC, +1>(buf, ls, F, d, tb.stw, lds, min(d.out_n, M));
   }
   for (int q = 0; q < ncl; ++q) {
     const int cc = curl ? q : comp;
@@ -1178,11 +1187,19 @@ __device__ __forceinline__ void run_single(const PassDesc& d, const void* in, vo
 
 // The descriptor lives in device memory (uniform loads); the buffers of this solve are
 // kernel arguments.
-// PIPE = 1: the persistent pipelined loop (compile-time lengths that allow it, and a
-// descriptor with persist = 1); PIPE = 0: one tile per workgroup with the twiddle tables
-// read from global memory, which leaves LDS for more workgroups per CU.
+// PIPE = 1: the pipelined kernel, with the twiddle tables staged in LDS (a persistent
+// grid, or one tile per workgroup); PIPE = 0: one tile per workgroup with the tables read
+// from global memory, which leaves LDS for more workgroups per CU.  The plain kinds of
+// the latter are held to at most 168 VGPRs (three waves per SIMD), which they fit
+// without spilling; the fused kinds would spill there and keep the compiler's choice.
+template <int KIND, int PIPE>
+constexpr int min_waves_per_simd() {
+  return (PIPE == 0 && !fused_of(KIND) && KIND != K_ANY) ? 3 : 1;
+}
+
 template <typename T, int MC, int KIND, int PIPE>
-__global__ __launch_bounds__(kThreads) void pass_kernel(const PassDesc* __restrict__ dp,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(min_waves_per_simd<KIND, PIPE>())))
+void pass_kernel(const PassDesc* __restrict__ dp,
                                                         const void* in, void* out) {
   extern __shared__ __align__(16) char smem[];
   if constexpr (PIPE && pipelined_kernel((int)sizeof(T), MC)) run_pipelined<T, MC, KIND>(*dp, in, out, smem);
