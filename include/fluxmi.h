@@ -152,7 +152,10 @@ int fm_plan_tiling(fm_plan p, int lines_per_tile[5], int tiles[5], int persist[5
  * into the workspace and waits for that copy on hip_stream.  fm_batch_run enqueues the
  * kernels only (no copies, no allocation, no host synchronisation), so it can be
  * recorded into a HIP graph and replayed; each replay recomputes the outputs from the
- * current contents of the right-hand sides.  The plans must outlive the batch.
+ * current contents of the right-hand sides.  FP32 batches run their solves side by side
+ * on up to 8 streams of the batch's own (default priority), forked from hip_stream and
+ * joined back into it with events, so that hip_stream's later work (and a capture of
+ * hip_stream) sees every solve finished.  The plans must outlive the batch.
  * Errors: as fm_solve_batched; FM_E_NULL for a null handle. */
 typedef struct fm_batch_s* fm_batch;
 int fm_batch_prepare(fm_batch* out, int count, const fm_plan* plans, const void* const* rhs_dev,

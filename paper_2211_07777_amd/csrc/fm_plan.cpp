@@ -940,6 +940,9 @@ thread_local BatchStaging* g_stage_ptr = nullptr;
 // A prepared batch: FP64 batches hold one launch per pass and length class (descriptor
 // tables in the workspace); FP32 batches hold the per-request buffers of plan-by-plan
 // launches.
+// Streams a prepared FP32 batch spreads its solves over.
+constexpr int kBatchLanes = 8;
+
 struct fm_batch_s {
   int prec = 0;
   std::vector<fm_plan_s*> plans;
@@ -951,6 +954,18 @@ struct fm_batch_s {
   };
   std::vector<Group> groups;
   char* dev_tables = nullptr;
+  // prepared FP32 batches: the plans are spread over these streams (default priority),
+  // forked from and joined back into the caller's stream with events
+  std::vector<hipStream_t> lanes;
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> joins;
+  ~fm_batch_s() {
+    for (hipEvent_t e : joins)
+      if (e) (void)hipEventDestroy(e);
+    if (fork) (void)hipEventDestroy(fork);
+    for (hipStream_t s : lanes)
+      if (s) (void)hipStreamDestroy(s);
+  }
 };
 
 namespace {
@@ -1037,9 +1052,26 @@ int build_batch(int count, const fm_plan* plans, const void* const* rhs_dev, voi
 
 int run_batch(const fm_batch_s& b, hipStream_t st) {
   if (b.prec == FM_F32) {
+    const size_t K = b.lanes.size();
+    if (K == 0) {
+      for (size_t i = 0; i < b.plans.size(); ++i) {
+        const int rc = launch_all(b.plans[i], &b.ins[5 * i], &b.outs[5 * i], st);
+        if (rc) return rc;
+      }
+      return FM_OK;
+    }
+    // independent solves side by side: plan i on lane i mod K, after everything enqueued
+    // on st so far; st then waits for every lane (a fork and join that a graph capture
+    // of st records as parallel branches)
+    FM_HIP(hipEventRecord(b.fork, st));
+    for (size_t k = 0; k < K; ++k) FM_HIP(hipStreamWaitEvent(b.lanes[k], b.fork, 0));
     for (size_t i = 0; i < b.plans.size(); ++i) {
-      const int rc = launch_all(b.plans[i], &b.ins[5 * i], &b.outs[5 * i], st);
+      const int rc = launch_all(b.plans[i], &b.ins[5 * i], &b.outs[5 * i], b.lanes[i % K]);
       if (rc) return rc;
+    }
+    for (size_t k = 0; k < K; ++k) {
+      FM_HIP(hipEventRecord(b.joins[k], b.lanes[k]));
+      FM_HIP(hipStreamWaitEvent(st, b.joins[k], 0));
     }
     return FM_OK;
   }
@@ -1413,6 +1445,20 @@ int fm_batch_prepare(fm_batch* out, int count, const fm_plan* plans, const void*
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
     hipError_t e = hipMemcpyAsync(b->dev_tables, host.data(), host.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+      g_last_hip = (int)e;
+      rc = FM_E_HIP;
+    }
+  }
+  if (rc == FM_OK && b->prec == FM_F32) {
+    const int K = count < kBatchLanes ? count : kBatchLanes;
+    hipError_t e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+    b->lanes.assign(K, nullptr);
+    b->joins.assign(K, nullptr);
+    for (int k = 0; k < K && e == hipSuccess; ++k) {
+      e = hipStreamCreateWithFlags(&b->lanes[k], hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&b->joins[k], hipEventDisableTiming);
+    }
     if (e != hipSuccess) {
       g_last_hip = (int)e;
       rc = FM_E_HIP;
