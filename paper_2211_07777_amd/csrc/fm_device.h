@@ -320,9 +320,13 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, int ls, int F, int M, int
   __syncthreads();
 }
 
-template <typename T, int M, int R, int Ns, int S, class P, class Load>
+// Destination of the last stage's outputs: NoSink writes them to LDS (natural order);
+// any other sink is called as sink(line, slot, value) for the kept slots instead.
+struct NoSink {};
+
+template <typename T, int M, int R, int Ns, int S, class P, class Load, class Sink>
 __device__ __forceinline__ void fft_stage_ct(cpx<T>* buf, int ls, int F, P stw, Load& load,
-                                             int keep) {
+                                             int keep, const Sink& sink) {
   constexpr int NB = (elems_per_thread((int)sizeof(T), M) + R - 1) / R;
   constexpr int MR = M / R;
   cpx<T> v[NB][R];
@@ -364,21 +368,26 @@ __device__ __forceinline__ void fft_stage_ct(cpx<T>* buf, int ls, int F, P stw, 
 #pragma unroll
       for (int q = 0; q < R; ++q) {
         // the last stage (Ns R = M) writes slot t + q Ns: only the first `keep` are read
-        if (Ns * R < M || base + q * Ns < keep) row[pad16(base + q * Ns)] = v[i][q];
+        if constexpr (Ns * R == M && !std::is_same<Sink, NoSink>::value) {
+          if (base + q * Ns < keep) sink(lin[i], base + q * Ns, v[i][q]);
+        } else {
+          if (Ns * R < M || base + q * Ns < keep) row[pad16(base + q * Ns)] = v[i][q];
+        }
       }
     }
   }
   __syncthreads();
 }
 
-template <typename T, int M, int S, int s, int Ns, class P, class Load>
-__device__ __forceinline__ void stages_ct(cpx<T>* buf, int ls, int F, P stw, Load& load, int keep) {
+template <typename T, int M, int S, int s, int Ns, class P, class Load, class Sink>
+__device__ __forceinline__ void stages_ct(cpx<T>* buf, int ls, int F, P stw, Load& load, int keep,
+                                          const Sink& sink) {
   constexpr int R = radix_at(M, s, Prec<T>::RMAX);
   if constexpr (R != 0) {
     fft_stage_ct<T, M, R, Ns, S>(buf, ls, F, stw + stage_table_offset(M, s, Prec<T>::RMAX), load,
-                                 keep);
+                                 keep, sink);
     auto lds = [buf, ls](int line, int idx) { return buf[line * ls + pad16(idx)]; };
-    stages_ct<T, M, S, s + 1, Ns * R>(buf, ls, F, stw, lds, keep);
+    stages_ct<T, M, S, s + 1, Ns * R>(buf, ls, F, stw, lds, keep, sink);
   }
 }
 
@@ -403,7 +412,7 @@ template <typename T, int MC, int S, class P, class Load>
 __device__ __forceinline__ void fft_lines(cpx<T>* buf, int ls, int F, const PassDesc& d, P stw,
                                           Load& load0, int keep = 1 << 30) {
   if constexpr (MC > 1) {
-    stages_ct<T, MC, S, 0, 1>(buf, ls, F, stw, load0, keep);
+    stages_ct<T, MC, S, 0, 1>(buf, ls, F, stw, load0, keep, NoSink{});
   } else {
     constexpr int EL = elems_per_thread((int)sizeof(T), MC);
     const GTab<T> tw = gptr<cpx<T>>(d.tw);  // runtime lengths: the 4M table in global memory
@@ -839,6 +848,23 @@ __device__ void fused_compute(const PassDesc& d, void* out, const TileIdx& ti, c
       const T g = gl[line * FL + fold_index(idx, fl)];
       return cpx<T>{z.x * g, z.y * g};
     };
+    if constexpr (MC > 1) {
+      if (d.out_s_line == 1) {
+        // contiguous output lines: the last inverse stage's lanes hold consecutive slots
+        // of a line, so they store to global memory directly (no LDS pass, no store loop)
+        cpx<T>* o = reinterpret_cast<cpx<T>*>(out) + comp * d.out_s_comp + c * d.out_s_c +
+                    b0 * d.out_s_b;
+        const int64_t sb = d.out_s_b;
+        const int on = d.out_n;
+        auto sink = [o, sb, on](int l, int j, const cpx<T>& v) {
+          cpx<T>* r = o + l * sb;
+          r[j] = v;
+          if (j + MC < on) r[j + MC] = v;  // periodic duplicate beyond one period
+        };
+        stages_ct<T, MC, +1, 0, 1>(buf, ls, F, tb.stw, lds_g, min(on, M), sink);
+        return;
+      }
+    }
     fft_lines<T, MC, +1>(buf, ls, F, d, tb.stw, lds_g, min(d.out_n, M));
   } else {
     const T wc = signed_wave<T>(c, d.g.M_c, T(d.g.dw_c));
