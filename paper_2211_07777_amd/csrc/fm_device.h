@@ -687,6 +687,22 @@ __device__ void plain_compute(const PassDesc& d, void* out, const TileIdx& ti, c
     GatherCplx<T> g{reinterpret_cast<const cpx<T>*>(smem), rs, d.n_data};
     // complex lines are written from their first out_n slots (cropped inverse)
     const int keep = scatter == S_CPLX ? min(d.out_n, M) : M;
+    if constexpr (MC > 1) {
+      if (scatter == S_CPLX && d.out_s_line == 1) {
+        // contiguous output lines: the last stage stores them directly
+        cpx<T>* o = reinterpret_cast<cpx<T>*>(out) + out_off;
+        const int64_t sb = d.out_s_b;
+        const int on = d.out_n;
+        auto sink = [o, sb, on](int l, int j, const cpx<T>& v) {
+          cpx<T>* r = o + l * sb;
+          r[j] = v;
+          if (j + MC < on) r[j + MC] = v;
+        };
+        if (sign < 0) stages_ct<T, MC, -1, 0, 1>(buf, ls, F, tb.stw, g, keep, sink);
+        else stages_ct<T, MC, +1, 0, 1>(buf, ls, F, tb.stw, g, keep, sink);
+        return;
+      }
+    }
     if (sign < 0) fft_lines<T, MC, -1>(buf, ls, F, d, tb.stw, g, keep);
     else fft_lines<T, MC, +1>(buf, ls, F, d, tb.stw, g, keep);
   } else if (gather == G_REAL2) {
@@ -899,6 +915,23 @@ __device__ void fused_compute(const PassDesc& d, void* out, const TileIdx& ti, c
         });
     __syncthreads();
     auto lds = [buf, ls](int line, int idx) { return buf[line * ls + pad16(idx)]; };
+    if constexpr (MC > 1) {
+      if (d.out_s_line == 1) {
+        // contiguous output lines: component q's line l (FFT line q nl + l) is stored
+        // by the last inverse stage directly
+        cpx<T>* o = reinterpret_cast<cpx<T>*>(out) + c * d.out_s_c + b0 * d.out_s_b;
+        const int64_t sb = d.out_s_b, sq = d.out_s_comp;
+        const int on = d.out_n;
+        auto sink = [o, sb, sq, on, nl](int line, int j, const cpx<T>& v) {
+          const int q = line >= 2 * nl ? 2 : (line >= nl ? 1 : 0);
+          cpx<T>* r = o + q * sq + (line - q * nl) * sb;
+          r[j] = v;
+          if (j + MC < on) r[j + MC] = v;
+        };
+        stages_ct<T, MC, +1, 0, 1>(buf, ls, F, tb.stw, lds, min(on, M), sink);
+        return;
+      }
+    }
     fft_lines<T, MC, +1>(buf, ls, F, d, tb.stw, lds, min(d.out_n, M));
   }
   for (int q = 0; q < ncl; ++q) {
