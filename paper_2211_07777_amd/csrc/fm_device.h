@@ -710,6 +710,27 @@ __device__ void plain_compute(const PassDesc& d, void* out, const TileIdx& ti, c
     fft_lines<T, MC, -1>(buf, ls, F, d, tb.stw, g);
   } else if (gather == G_HERM2) {
     GatherHerm2<T> g{reinterpret_cast<const cpx<T>*>(smem), rs, M, nl};
+    if constexpr (MC > 1) {
+      if (scatter == S_REAL2 && !d.has_fix && d.out_s_line == 1) {
+        // contiguous real output lines without fix-ups: FFT line f holds tile lines 2f
+        // (real part) and 2f + 1 (imaginary part); the last stage stores them directly
+        T* o = reinterpret_cast<T*>(out) + out_off;
+        const int64_t sb = d.out_s_b;
+        const int on = d.out_n;
+        auto sink = [o, sb, on, nl](int f, int j, const cpx<T>& v) {
+          T* r0 = o + (2 * f) * sb;
+          r0[j] = v.x;
+          if (j + MC < on) r0[j + MC] = v.x;
+          if (2 * f + 1 < nl) {
+            T* r1 = r0 + sb;
+            r1[j] = v.y;
+            if (j + MC < on) r1[j + MC] = v.y;
+          }
+        };
+        stages_ct<T, MC, +1, 0, 1>(buf, ls, F, tb.stw, g, min(on, M), sink);
+        return;
+      }
+    }
     fft_lines<T, MC, +1>(buf, ls, F, d, tb.stw, g, scatter == S_REAL2 ? min(d.out_n, M) : M);
   } else {
     GatherR2R<T, P> g{reinterpret_cast<const T*>(smem + d.raw_off), rs, d.in_n, nl, d.r2r, tw};
