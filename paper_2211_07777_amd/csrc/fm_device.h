@@ -460,6 +460,34 @@ struct GatherReal2 {  // two real lines packed as re + i im, zero padded
   }
 };
 
+// GatherCplx and GatherReal2 reading contiguous input lines straight from global memory
+// (p: the tile's first line, sb: the line stride in elements).
+template <typename T>
+struct GatherCplxG {
+  const __attribute__((address_space(1))) cpx<T>* p;
+  int64_t sb;
+  int n_data;
+  __device__ cpx<T> operator()(int f, int m) const {
+    if (m >= n_data) return {T(0), T(0)};
+    const auto& z = p[f * sb + m];
+    return {z.x, z.y};
+  }
+};
+
+template <typename T>
+struct GatherReal2G {
+  const __attribute__((address_space(1))) T* p;
+  int64_t sb;
+  int n_data, nl;
+  __device__ cpx<T> operator()(int f, int m) const {
+    if (m >= n_data) return {T(0), T(0)};
+    const int l = 2 * f;
+    const T a = p[l * sb + m];
+    const T b = (l + 1 < nl) ? p[(l + 1) * sb + m] : T(0);
+    return {a, b};
+  }
+};
+
 template <typename T>
 struct GatherHerm2 {  // two Hermitian half-spectra -> one full spectrum
   const cpx<T>* raw;
@@ -667,9 +695,11 @@ __device__ __forceinline__ void store_real(const PassDesc& d, void* out, const T
                   d.out_n, d.mag_out, d.B, d.mag_B, ti.b0, ti.c, d.fix, val);
 }
 
-template <typename T, int MC, int KIND, class P>
+// DIRECT: forward complex or real-to-complex lines read by the first FFT stage straight
+// from contiguous input lines at gin (the tile's first line) instead of the LDS raw tile.
+template <typename T, int MC, int KIND, bool DIRECT = false, class P>
 __device__ void plain_compute(const PassDesc& d, void* out, const TileIdx& ti, char* smem,
-                              const Tabs<P>& tb) {
+                              const Tabs<P>& tb, const void* gin = nullptr) {
   const int gather = KIND == K_ANY ? d.gather : gather_of(KIND);
   const int scatter = KIND == K_ANY ? d.scatter : scatter_of(KIND);
   const int sign = KIND == K_ANY ? d.sign : (KIND == K_C2C_I || KIND == K_C2R ? +1 : -1);
@@ -683,7 +713,13 @@ __device__ void plain_compute(const PassDesc& d, void* out, const TileIdx& ti, c
 
   // 2) FFT (first stage gathers from the raw tile, which aliases the FFT buffer)
   const int F = (gather == G_CPLX) ? nl : (nl + 1) / 2;
-  if (gather == G_CPLX) {
+  if constexpr (DIRECT && KIND == K_C2C_F) {
+    GatherCplxG<T> g{gptr<cpx<T>>(gin), d.in_s_b, d.n_data};
+    fft_lines<T, MC, -1>(buf, ls, F, d, tb.stw, g);
+  } else if constexpr (DIRECT && KIND == K_R2C) {
+    GatherReal2G<T> g{gptr<T>(gin), d.in_s_b, d.n_data, nl};
+    fft_lines<T, MC, -1>(buf, ls, F, d, tb.stw, g);
+  } else if (gather == G_CPLX) {
     GatherCplx<T> g{reinterpret_cast<const cpx<T>*>(smem), rs, d.n_data};
     // complex lines are written from their first out_n slots (cropped inverse)
     const int keep = scatter == S_CPLX ? min(d.out_n, M) : M;
@@ -1253,9 +1289,21 @@ __device__ __forceinline__ void run_single(const PassDesc& d, const void* in, vo
     const int tile = xcd_tile(blockIdx.x, gridDim.x, k, d.tiles);
     if (tile < 0) return;
     if (k > 0) __syncthreads();  // the previous tile's LDS reads are finished
+    const TileIdx ti = tile_index(d, tile);
+    if constexpr (MC > 1 && (KIND == K_C2C_F || (KIND == K_R2C && MC <= 512))) {
+      if (d.in_s_line == 1) {
+        // contiguous input lines: the first FFT stage reads them from global memory
+        // (measured slower for real-to-complex lines of 1024 and more, which keep the
+        // LDS tile)
+        const void* gin = reinterpret_cast<const char*>(in) +
+                          ((int64_t)ti.comp * d.in_s_comp + (int64_t)ti.c * d.in_s_c +
+                           (int64_t)ti.b0 * d.in_s_b) * (int64_t)sizeof(E);
+        plain_compute<T, MC, KIND, true>(d, out, ti, smem, global_tabs<T>(d), gin);
+        continue;
+      }
+    }
     RegStage<T, E, U * NCL> v;
     GreenStage<T, UG> gs;
-    const TileIdx ti = tile_index(d, tile);
     fetch<U, NCL, (MC <= 1), E>(v, d, in, ti);
     if constexpr (fused_of(KIND)) fetch_green<T, UG>(gs, d, ti);
     commit<U, NCL, E>(v, d, ti, smem);
