@@ -90,20 +90,30 @@ int fm_plan_create(fm_plan* out, const int n[3], const double h[3], const int bc
  * uses it is still in flight.  NULL is accepted and ignored. */
 int fm_plan_destroy(fm_plan p);
 
-/* Bytes of device workspace a solve with this plan needs (2 spectral buffers per
- * component, sized for the padded volumes). */
+/* Bytes of device workspace a solve with this plan needs: per component, the spectrum
+ * after the first transform and the spectrum after the first two (Sec. III: the data
+ * between two topology switches), each with its complex or real extent per axis
+ * (Sec. II-B, II-C); the zero padding of unbounded directions is never stored.
+ * Errors: FM_E_NULL. */
 int fm_plan_workspace_bytes(fm_plan p, size_t* bytes);
 
-/* The user array extents (nx, ny, nz): N or N + 1 per axis. */
+/* The user array extents (nx, ny, nz): N cells, or N + 1 nodes, per axis (the point
+ * numbering of Sec. II-A).  Errors: FM_E_NULL. */
 int fm_plan_shape(fm_plan p, int user_dims[3]);
 
-/* Solve for one set of right-hand sides.
+/* Solve for one set of right-hand sides: forward transforms along the three axes, the
+ * product with the Green's spectrum (Poisson; the convolution of Sec. II) or with the
+ * Green's spectrum times i*omega x (Biot-Savart; Sec. V), inverse transforms and the
+ * crop of the padded directions (Sec. II-C), in the axis order of Sec. III.
  *   rhs_dev   [ncomp][nz][ny][nx] input, never written
  *   out_dev   same shape; may alias rhs_dev (in-place mode)
  *   workspace_dev  at least fm_plan_workspace_bytes bytes, or NULL to use the plan's
- *             own workspace (then concurrent solves with one plan must not overlap)
- * Output conventions: nodes on an odd face are exactly 0; the node-centred periodic
- * duplicate f_N equals f_0; input values at those positions are ignored. */
+ *             own workspace, allocated on first use (then concurrent solves with one plan
+ *             must not overlap)
+ * The caller keeps ownership of every buffer.  Output conventions: nodes on an odd face
+ * are exactly 0; the node-centred periodic duplicate f_N equals f_0 (Sec. II-A); input
+ * values at those positions are ignored.
+ * Errors: FM_E_NULL, FM_E_NOMEM (the plan's own workspace), FM_E_HIP (a launch). */
 int fm_solve(fm_plan p, const void* rhs_dev, void* out_dev, void* workspace_dev, void* hip_stream);
 
 /* Run passes [first_pass, last_pass] (0-based, of the five: 0 first-axis forward,
@@ -145,6 +155,15 @@ int fm_plan_device_bytes(fm_plan p, size_t* bytes);
  * the tables in LDS, 2 one tile per workgroup with the tables read from global memory. */
 int fm_plan_tiling(fm_plan p, int lines_per_tile[5], int tiles[5], int persist[5]);
 
+/* Set the tiling of every pass, as fm_plan_tiling reports it (for example a tiling that
+ * fm_plan_tune found earlier for the same problem and device): lines_per_tile[i] lines
+ * per tile and launch mode persist[i] for pass i.  The result of a solve can change at
+ * the rounding level only (as after fm_plan_tune).  The descriptors are uploaded on
+ * hip_stream, which is synchronised.  Not to be called while solves with this plan are
+ * in flight.  Errors: FM_E_NULL; FM_E_ARG if a pass cannot run with exactly that
+ * tiling (register, LDS or addressing limits of its kernel); FM_E_HIP. */
+int fm_plan_set_tiling(fm_plan p, const int lines_per_tile[5], const int persist[5], void* hip_stream);
+
 /* A batch prepared once and launched many times: the same work as fm_solve_batched on
  * fixed buffers.  fm_batch_prepare binds the plans, right-hand sides, outputs and
  * workspace (arguments as for fm_solve_batched; the workspace must stay allocated and
@@ -169,30 +188,38 @@ int fm_batch_destroy(fm_batch b);
  * whose tables may use up to plan_budget_bytes (least recently used plans with no
  * waiting or running request are destroyed beyond that).  Each request is one solve
  * (fm_solve semantics; rhs_dev / out_dev are the caller's and must stay valid until the
- * request has finished).  Requests wait in FIFO order until one of `slots` device
- * streams and their workspace are free; then they run, overlapping on the device with
- * the other running requests.  fm_server_progress retires finished requests, admits
- * waiting ones and returns the finished tickets (in completion order); it never
- * blocks.  fm_server_wait_all blocks until every submitted request has finished.
- * tune_plans != 0 autotunes each new plan (fm_plan_tune).  One host thread drives a
- * server.  Errors: FM_E_ARG (slots outside 1..64, zero budget), FM_E_NOMEM (arena, or a
- * request whose workspace exceeds the whole budget), FM_E_HIP, and those of
- * fm_plan_create / fm_solve for a request. */
+ * request has finished).  fm_server_submit records an event on hip_stream, the
+ * stream on which the caller produced rhs_dev and last used out_dev (NULL: the null
+ * stream): the request's solve runs after that work.  A request that needs a new plan
+ * has it generated on the server's own stream; neither submission nor admission waits
+ * for the device (except with tune_plans, which times the new plan's kernels).
+ * Requests wait in FIFO order until one of `slots` device streams and their workspace
+ * are free; then they run, overlapping on the device with the other running requests.
+ * fm_server_progress retires finished requests, admits waiting ones and returns the
+ * finished tickets in completion order, with status[i] FM_OK or the error that kept
+ * the request from running (status may be NULL); it never blocks.  fm_server_wait_all
+ * blocks until every submitted request has finished.  tune_plans != 0 autotunes each
+ * new plan (fm_plan_tune).  One host thread drives a server.  Errors: FM_E_ARG (slots
+ * outside 1..64, zero budget), FM_E_NOMEM (arena, or a request whose workspace exceeds
+ * the whole budget), FM_E_HIP, and those of fm_plan_create for a request (the request
+ * is then not queued). */
 typedef struct fm_server_s* fm_server;
 typedef struct {
-  long long submitted, finished;               /* requests */
+  long long submitted, finished;               /* requests (finished counts failed) */
   long long plan_hits, plan_misses, plan_evictions;
   size_t peak_workspace_bytes;                 /* arena bytes in use, maximum */
   int peak_inflight;                           /* requests running at once, maximum */
   int cached_plans, waiting, running;          /* now */
   size_t plan_bytes;                           /* device bytes of the cached plans, now */
+  long long failed;                            /* requests finished with an error */
 } fm_server_stats;
 int fm_server_create(fm_server* out, size_t workspace_budget_bytes, size_t plan_budget_bytes,
                      int slots, int tune_plans);
 int fm_server_submit(fm_server s, const int n[3], const double h[3], const int bc[3][2], int layout,
                      int green, int prec, int kind, int ncomp, const void* rhs_dev, void* out_dev,
-                     long long* ticket);
-int fm_server_progress(fm_server s, long long* finished, int max_finished, int* n_finished);
+                     void* hip_stream, long long* ticket);
+int fm_server_progress(fm_server s, long long* finished, int* status, int max_finished,
+                       int* n_finished);
 int fm_server_wait_all(fm_server s);
 int fm_server_get_stats(fm_server s, fm_server_stats* stats);
 int fm_server_destroy(fm_server s);

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfluxmi.so")
-HEADERS = ["fm_pass.h", "fm_device.h", "fm_launch.h"]
+HEADERS = ["fm_pass.h", "fm_device.h", "fm_launch.h", "fm_internal.h"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -46,9 +46,17 @@ def _sources():
         [os.path.join(CSRC, h) for h in HEADERS] + [os.path.join(os.path.dirname(HERE), "include", "fluxmi.h")]
 
 
-def _compile(unit):
+def _compile(unit, force=True):
     src, obj, defs = unit
     out = os.path.join(OBJ, obj)
+    if not force and os.path.exists(out):
+        device = src.endswith(("fm_inst.hip", "fm_gen.hip"))  # include fm_device.h only
+        heads = ["fm_pass.h", "fm_device.h", "fm_launch.h"] if device else ["fm_pass.h", "fm_internal.h"]
+        deps = [src] + [os.path.join(CSRC, h) for h in heads] + [os.path.abspath(__file__)]
+        if not device:
+            deps.append(os.path.join(os.path.dirname(HERE), "include", "fluxmi.h"))
+        if os.path.getmtime(out) >= max(os.path.getmtime(d) for d in deps):
+            return out
     cmd = [HIPCC] + FLAGS + defs + ["-c", src, "-o", out]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
@@ -57,14 +65,15 @@ def _compile(unit):
 
 
 def build_library(force: bool = True, jobs: int | None = None) -> str:
-    """Compile libfluxmi.so; with force=False only when a source is newer."""
+    """Compile libfluxmi.so; with force=False only the objects older than their sources
+    (and only when some source is newer than the library)."""
     if not force and os.path.exists(LIB):
         if os.path.getmtime(LIB) >= max(os.path.getmtime(p) for p in _sources()):
             return LIB
     os.makedirs(OBJ, exist_ok=True)
     jobs = jobs or min(16, os.cpu_count() or 4)
     with ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, _units()))
+        objs = list(ex.map(lambda u: _compile(u, force), _units()))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -75,4 +84,5 @@ def build_library(force: bool = True, jobs: int | None = None) -> str:
 
 
 if __name__ == "__main__":
-    print(build_library(force=True))
+    import sys
+    print(build_library(force="--incremental" not in sys.argv))

@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "../../include/fluxmi.h"
+#include "fm_internal.h"
 #include "fm_pass.h"
 
 namespace fm {
@@ -251,6 +252,13 @@ struct fm_plan_s {
   std::map<int, void*> stw;
   std::map<int, void*> tw64;
   void* ws_internal = nullptr;
+  std::mutex ws_mu;  // guards the lazy allocation of ws_internal
+  // Deferred creation (serving loop): the generation kernels may still run when the
+  // plan is returned.  `ready` completes with them; the FP64 temporaries in gen_free
+  // and the host copies of the generation descriptors are released after it.
+  hipEvent_t ready = nullptr;
+  std::vector<void*> gen_free;
+  std::vector<fm::PassDesc> gen_desc;
   int device = 0;
   size_t table_bytes = 0;  // device memory of the plan's tables (Green, twiddles, descriptors)
 };
@@ -315,12 +323,22 @@ TileLds tile_lds(const fm::PassDesc& d, int B, size_t elem, int comps, bool fuse
 // Kernel length class that fixes the values per thread of a pass.
 int pass_class(const fm::PassDesc& d) { return d.long_rt ? fm::kRtLong : d.M; }
 
+// Whether a pass runs in the compile-time-length kernel of its FFT length (else in the
+// runtime-length kernel).  FP32 fused real-to-real passes of length 32 are kept on the
+// runtime-length kernel: the compile-time one ran only in a test that faulted the GPU,
+// and nothing has shown it free of that fault.
+bool compile_time_kernel(const fm::PassDesc& d, size_t elem) {
+  if (d.long_rt || !fm::is_fast_len(d.M)) return false;
+  if (elem == 4 && d.fused && d.gather == fm::G_R2R && d.M == 32) return false;
+  return true;
+}
+
 // Twiddle entries the persistent kernel of this pass copies to LDS: the stage table,
 // and for real-to-real gathers the first 2M entries of the 4M table (pre- and
 // post-twiddles).  Descriptors with lds_tabs = 0 read them from global memory.
 void set_lds_tables(fm::PassDesc* d, size_t elem) {
   d->stw_n = d->tw_n = 0;
-  if (!d->lds_tabs || d->long_rt || !fm::is_fast_len(d->M) || !fm::pipelined_kernel((int)elem, d->M))
+  if (!d->lds_tabs || !compile_time_kernel(*d, elem) || !fm::pipelined_kernel((int)elem, d->M))
     return;
   d->stw_n = fm::stage_table_size(d->M, fm::max_radix((int)elem));
   if (d->gather == fm::G_R2R) d->tw_n = 2 * d->M;
@@ -412,8 +430,21 @@ void set_transform(fm::PassDesc* d, const AxisPlan& a, bool forward, bool fused_
   }
 }
 
+// Release the generation temporaries of a plan (its generation work has completed).
+void release_generation(fm_plan_s* p) {
+  for (void* ptr : p->gen_free) (void)hipFree(ptr);
+  p->gen_free.clear();
+  p->gen_desc.clear();
+  for (auto& kv : p->tw64) (void)hipFree(kv.second);
+  p->tw64.clear();
+}
+
+// Twiddle tables and the Green's spectrum of a plan, generated on stream st.  With
+// deferred = false the call waits for the generation and releases its temporaries; with
+// deferred = true it records p->ready after the generation instead and leaves the
+// release to finish_generation.
 template <typename T>
-int make_tables_and_green(fm_plan_s* p, hipStream_t st) {
+int make_tables_and_green(fm_plan_s* p, hipStream_t st, bool deferred) {
   // twiddle tables for every FFT length of the passes
   for (int i = 0; i < 5; ++i) {
     const int M = p->pass[i].M;
@@ -428,7 +459,7 @@ int make_tables_and_green(fm_plan_s* p, hipStream_t st) {
   // per-stage tables of the lengths with compile-time kernels
   for (int i = 0; i < 5; ++i) {
     const int M = p->pass[i].M;
-    if (!fm::is_fast_len(M) || p->pass[i].long_rt) continue;
+    if (!compile_time_kernel(p->pass[i], p->elem)) continue;
     if (tile_in_span_bytes(p->pass[i], p->elem) >= (int64_t(1) << 32)) continue;
     if (!p->stw.count(M)) {
       void* ptr = nullptr;
@@ -472,15 +503,15 @@ int make_tables_and_green(fm_plan_s* p, hipStream_t st) {
   const int64_t ns = (int64_t)Fs[0] * Fs[1] * Fs[2];
   double* S = nullptr;
   if (hipMalloc(&S, sizeof(double) * ns) != hipSuccess) return FM_E_NOMEM;
+  p->gen_free.push_back(S);
   int rc = FM_OK;
   FM_HIP(fm::launch_green_sample(S, g, st));
   int64_t sstr[3] = {(int64_t)Fs[1] * Fs[2], Fs[2], 1};
-  fm::PassDesc gdesc[3];
+  p->gen_desc.assign(3, fm::PassDesc{});  // host copies stay alive until the copies ran
+  fm::PassDesc* gdesc = p->gen_desc.data();
   fm::PassDesc* gdev = nullptr;
-  if (hipMalloc(&gdev, sizeof(fm::PassDesc) * 3) != hipSuccess) {
-    (void)hipFree(S);
-    return FM_E_NOMEM;
-  }
+  if (hipMalloc(&gdev, sizeof(fm::PassDesc) * 3) != hipSuccess) return FM_E_NOMEM;
+  p->gen_free.push_back(gdev);
   for (int i = 0; i < 3 && rc == FM_OK; ++i) {
     if (!g.unb[i]) continue;
     // DCT-I (REDFT00) of Fs[i] samples, in place along table axis i
@@ -544,26 +575,45 @@ int make_tables_and_green(fm_plan_s* p, hipStream_t st) {
     if (rc == FM_OK)
       FM_HIP(hipMemcpyAsync(p->dpass, p->pass, sizeof(fm::PassDesc) * 5, hipMemcpyHostToDevice, st));
   }
+  for (int i = 0; i < 3; ++i) p->GF[i] = F[i];
+  if (deferred && rc == FM_OK) {
+    FM_HIP(hipEventCreateWithFlags(&p->ready, hipEventDisableTiming));
+    FM_HIP(hipEventRecord(p->ready, st));
+    return FM_OK;
+  }
   hipError_t e = hipStreamSynchronize(st);
-  (void)hipFree(gdev);
-  (void)hipFree(S);
-  for (auto& kv : p->tw64) (void)hipFree(kv.second);
-  p->tw64.clear();
+  release_generation(p);
   if (rc) return rc;
   if (e != hipSuccess) { g_last_hip = (int)e; return FM_E_HIP; }
-  for (int i = 0; i < 3; ++i) p->GF[i] = F[i];
   return FM_OK;
 }
 
 void free_plan(fm_plan_s* p) {
   if (!p) return;
+  if (p->ready) {
+    (void)hipEventSynchronize(p->ready);
+    (void)hipEventDestroy(p->ready);
+  } else if (!p->gen_free.empty()) {
+    (void)hipDeviceSynchronize();  // a failed creation: its generation work may be queued
+  }
+  release_generation(p);
   for (auto& kv : p->tw) (void)hipFree(kv.second);
   for (auto& kv : p->stw) (void)hipFree(kv.second);
-  for (auto& kv : p->tw64) (void)hipFree(kv.second);
   if (p->G) (void)hipFree(p->G);
   if (p->dpass) (void)hipFree(p->dpass);
   if (p->ws_internal) (void)hipFree(p->ws_internal);
   delete p;
+}
+
+// The plan's own workspace, allocated on first use (under the plan's lock, so that two
+// host threads solving with one plan allocate it once); nullptr if allocation fails.
+char* own_workspace(fm_plan_s* p) {
+  std::lock_guard<std::mutex> lock(p->ws_mu);
+  if (!p->ws_internal && hipMalloc(&p->ws_internal, p->ws_bytes) != hipSuccess) {
+    p->ws_internal = nullptr;
+    return nullptr;
+  }
+  return reinterpret_cast<char*>(p->ws_internal);
 }
 
 int pass_kind(const fm::PassDesc& d) {
@@ -1093,6 +1143,82 @@ namespace fm {
 void set_last_hip_error(int e) { g_last_hip = e; }
 }  // namespace fm
 
+namespace {
+
+int check_enums(int layout, int green, int prec, int kind, int ncomp) {
+  if (layout != FM_CELL && layout != FM_NODE) return FM_E_KIND;
+  if (green != FM_GREEN_CHAT2 && green != FM_GREEN_CHAT2_VOL) return FM_E_KIND;
+  if (prec != FM_F64 && prec != FM_F32) return FM_E_KIND;
+  if (kind != FM_POISSON && kind != FM_BIOT_SAVART) return FM_E_KIND;
+  if (ncomp < 1 || ncomp > 64) return FM_E_KIND;
+  return FM_OK;
+}
+
+fm_plan_s* new_plan(const int n[3], const double h[3], const int bc[3][2], int layout, int green,
+                    int prec, int kind, int ncomp) {
+  fm_plan_s* p = new (std::nothrow) fm_plan_s();
+  if (!p) return nullptr;
+  for (int a = 0; a < 3; ++a) {
+    p->n[a] = n[a];
+    p->h[a] = h[a];
+    p->bc[a][0] = bc[a][0];
+    p->bc[a][1] = bc[a][1];
+  }
+  p->layout = layout;
+  p->green = green;
+  p->prec = prec;
+  p->kind = kind;
+  p->ncomp = ncomp;
+  return p;
+}
+
+int create_plan(fm_plan* out, const int n[3], const double h[3], const int bc[3][2], int layout,
+                int green, int prec, int kind, int ncomp, hipStream_t st, bool deferred) {
+  if (!out || !n || !h || !bc) return FM_E_NULL;
+  *out = nullptr;
+  int rc = check_enums(layout, green, prec, kind, ncomp);
+  if (rc) return rc;
+  fm_plan_s* p = new_plan(n, h, bc, layout, green, prec, kind, ncomp);
+  if (!p) return FM_E_NOMEM;
+  rc = build_plan(p);
+  if (rc == FM_OK) {
+    const hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+      g_last_hip = (int)e;
+      rc = FM_E_HIP;
+    }
+  }
+  if (rc == FM_OK)
+    rc = (prec == FM_F64) ? make_tables_and_green<double>(p, st, deferred)
+                          : make_tables_and_green<float>(p, st, deferred);
+  if (rc != FM_OK) {
+    free_plan(p);
+    return rc;
+  }
+  *out = p;
+  return FM_OK;
+}
+
+}  // namespace
+
+namespace fm {
+int plan_create_deferred(fm_plan* out, const int n[3], const double h[3], const int bc[3][2],
+                         int layout, int green, int prec, int kind, int ncomp, hipStream_t st,
+                         hipEvent_t* ready) {
+  if (!ready) return FM_E_NULL;
+  const int rc = create_plan(out, n, h, bc, layout, green, prec, kind, ncomp, st, true);
+  *ready = rc == FM_OK ? (*out)->ready : nullptr;
+  return rc;
+}
+
+void plan_generation_done(fm_plan p) {
+  if (!p || !p->ready) return;
+  release_generation(p);
+  (void)hipEventDestroy(p->ready);
+  p->ready = nullptr;
+}
+}  // namespace fm
+
 extern "C" {
 
 const char* fm_error_string(int status) {
@@ -1113,67 +1239,17 @@ int fm_last_hip_error(void) { return g_last_hip; }
 
 int fm_plan_create(fm_plan* out, const int n[3], const double h[3], const int bc[3][2], int layout,
                    int green, int prec, int kind, int ncomp, void* hip_stream) {
-  if (!out || !n || !h || !bc) return FM_E_NULL;
-  *out = nullptr;
-  if (layout != FM_CELL && layout != FM_NODE) return FM_E_KIND;
-  if (green != FM_GREEN_CHAT2 && green != FM_GREEN_CHAT2_VOL) return FM_E_KIND;
-  if (prec != FM_F64 && prec != FM_F32) return FM_E_KIND;
-  if (kind != FM_POISSON && kind != FM_BIOT_SAVART) return FM_E_KIND;
-  if (ncomp < 1 || ncomp > 64) return FM_E_KIND;
-  fm_plan_s* p = new (std::nothrow) fm_plan_s();
-  if (!p) return FM_E_NOMEM;
-  for (int a = 0; a < 3; ++a) {
-    p->n[a] = n[a];
-    p->h[a] = h[a];
-    p->bc[a][0] = bc[a][0];
-    p->bc[a][1] = bc[a][1];
-  }
-  p->layout = layout;
-  p->green = green;
-  p->prec = prec;
-  p->kind = kind;
-  p->ncomp = ncomp;
-  int rc = build_plan(p);
-  if (rc == FM_OK) {
-    const hipError_t e = hipGetDevice(&p->device);
-    if (e != hipSuccess) {
-      g_last_hip = (int)e;
-      rc = FM_E_HIP;
-    }
-  }
-  if (rc == FM_OK) {
-    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
-    rc = (prec == FM_F64) ? make_tables_and_green<double>(p, st) : make_tables_and_green<float>(p, st);
-  }
-  if (rc != FM_OK) {
-    free_plan(p);
-    return rc;
-  }
-  *out = p;
-  return FM_OK;
+  return create_plan(out, n, h, bc, layout, green, prec, kind, ncomp,
+                     reinterpret_cast<hipStream_t>(hip_stream), false);
 }
 
 int fm_plan_inspect(const int n[3], const double h[3], const int bc[3][2], int layout, int green,
                     int prec, int kind, int ncomp, fm_plan_info* info) {
   if (!n || !h || !bc || !info) return FM_E_NULL;
-  if (layout != FM_CELL && layout != FM_NODE) return FM_E_KIND;
-  if (green != FM_GREEN_CHAT2 && green != FM_GREEN_CHAT2_VOL) return FM_E_KIND;
-  if (prec != FM_F64 && prec != FM_F32) return FM_E_KIND;
-  if (kind != FM_POISSON && kind != FM_BIOT_SAVART) return FM_E_KIND;
-  if (ncomp < 1 || ncomp > 64) return FM_E_KIND;
-  fm_plan_s* p = new (std::nothrow) fm_plan_s();
+  const int rc0 = check_enums(layout, green, prec, kind, ncomp);
+  if (rc0) return rc0;
+  fm_plan_s* p = new_plan(n, h, bc, layout, green, prec, kind, ncomp);
   if (!p) return FM_E_NOMEM;
-  for (int a = 0; a < 3; ++a) {
-    p->n[a] = n[a];
-    p->h[a] = h[a];
-    p->bc[a][0] = bc[a][0];
-    p->bc[a][1] = bc[a][1];
-  }
-  p->layout = layout;
-  p->green = green;
-  p->prec = prec;
-  p->kind = kind;
-  p->ncomp = ncomp;
   const int rc = build_plan(p);
   if (rc == FM_OK) {
     for (int a = 0; a < 3; ++a) {
@@ -1225,12 +1301,7 @@ int fm_solve(fm_plan p, const void* rhs_dev, void* out_dev, void* workspace_dev,
   if (!p || !rhs_dev || !out_dev) return FM_E_NULL;
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   char* ws = reinterpret_cast<char*>(workspace_dev);
-  if (!ws) {
-    if (!p->ws_internal) {
-      if (hipMalloc(&p->ws_internal, p->ws_bytes) != hipSuccess) return FM_E_NOMEM;
-    }
-    ws = reinterpret_cast<char*>(p->ws_internal);
-  }
+  if (!ws && !(ws = own_workspace(p))) return FM_E_NOMEM;
   const void* ins[5];
   void* outs[5];
   bind_buffers(p, rhs_dev, out_dev, ws, ins, outs);
@@ -1243,12 +1314,7 @@ int fm_solve_passes(fm_plan p, const void* rhs_dev, void* out_dev, void* workspa
   if (first_pass < 0 || last_pass > 4 || first_pass > last_pass) return FM_E_ARG;
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   char* ws = reinterpret_cast<char*>(workspace_dev);
-  if (!ws) {
-    if (!p->ws_internal) {
-      if (hipMalloc(&p->ws_internal, p->ws_bytes) != hipSuccess) return FM_E_NOMEM;
-    }
-    ws = reinterpret_cast<char*>(p->ws_internal);
-  }
+  if (!ws && !(ws = own_workspace(p))) return FM_E_NOMEM;
   const void* ins[5];
   void* outs[5];
   bind_buffers(p, rhs_dev, out_dev, ws, ins, outs);
@@ -1307,7 +1373,7 @@ int fm_solve_batched(int count, const fm_plan* plans, const void* const* rhs_dev
 // tables, 0 one tile per workgroup with LDS tables, 2 one tile per workgroup with global
 // tables (the only mode of the runtime-length and long FP64 kernels).
 int launch_mode(const fm::PassDesc& d, size_t elem) {
-  const bool pipelined = !d.long_rt && fm::is_fast_len(d.M) && fm::pipelined_kernel((int)elem, d.M);
+  const bool pipelined = compile_time_kernel(d, elem) && fm::pipelined_kernel((int)elem, d.M);
   if (!pipelined || !d.lds_tabs) return 2;
   return d.persist ? 1 : 0;
 }
@@ -1337,10 +1403,7 @@ int fm_plan_tune(fm_plan p, void* workspace_dev, void* hip_stream) {
   if (!p) return FM_E_NULL;
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   char* ws = reinterpret_cast<char*>(workspace_dev);
-  if (!ws) {
-    if (!p->ws_internal && hipMalloc(&p->ws_internal, p->ws_bytes) != hipSuccess) return FM_E_NOMEM;
-    ws = reinterpret_cast<char*>(p->ws_internal);
-  }
+  if (!ws && !(ws = own_workspace(p))) return FM_E_NOMEM;
   // scratch right-hand side and output (their values do not change the timing)
   const size_t ubytes = (size_t)p->Vu * p->ncomp * p->elem;
   void* rhs = nullptr;
@@ -1427,6 +1490,23 @@ int fm_plan_tiling(fm_plan p, int lines_per_tile[5], int tiles[5], int persist[5
     tiles[i] = p->pass[i].tiles;
     persist[i] = launch_mode(p->pass[i], p->elem);
   }
+  return FM_OK;
+}
+
+int fm_plan_set_tiling(fm_plan p, const int lines_per_tile[5], const int persist[5], void* hip_stream) {
+  if (!p || !lines_per_tile || !persist) return FM_E_NULL;
+  fm::PassDesc next[5];
+  for (int i = 0; i < 5; ++i) {
+    const int mode = persist[i];
+    if (lines_per_tile[i] < 1 || mode < 0 || mode > 2) return FM_E_ARG;
+    if (!retile(p, i, lines_per_tile[i], mode, &next[i])) return FM_E_ARG;
+    // exactly the requested tiling (retile takes the largest tile up to the bound)
+    if (next[i].B != lines_per_tile[i] || launch_mode(next[i], p->elem) != mode) return FM_E_ARG;
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  for (int i = 0; i < 5; ++i) p->pass[i] = next[i];
+  FM_HIP(hipMemcpyAsync(p->dpass, p->pass, sizeof(fm::PassDesc) * 5, hipMemcpyHostToDevice, st));
+  FM_HIP(hipStreamSynchronize(st));
   return FM_OK;
 }
 

@@ -26,7 +26,7 @@ EXPORTED = [
     "fm_error_string", "fm_last_hip_error", "fm_batch_prepare", "fm_batch_run", "fm_batch_destroy",
     "fm_plan_tune", "fm_plan_tiling", "fm_plan_device_bytes",
     "fm_server_create", "fm_server_submit", "fm_server_progress", "fm_server_wait_all",
-    "fm_server_get_stats", "fm_server_destroy",
+    "fm_server_get_stats", "fm_server_destroy", "fm_plan_set_tiling",
 ]
 
 
@@ -35,7 +35,7 @@ class ServerStats(ctypes.Structure):
                 ("plan_hits", ctypes.c_longlong), ("plan_misses", ctypes.c_longlong),
                 ("plan_evictions", ctypes.c_longlong), ("peak_workspace_bytes", ctypes.c_size_t),
                 ("peak_inflight", ctypes.c_int), ("cached_plans", ctypes.c_int), ("waiting", ctypes.c_int),
-                ("running", ctypes.c_int), ("plan_bytes", ctypes.c_size_t)]
+                ("running", ctypes.c_int), ("plan_bytes", ctypes.c_size_t), ("failed", ctypes.c_longlong)]
 
 
 class FluxmiError(RuntimeError):
@@ -91,12 +91,13 @@ def library():
     L.fm_batch_run.argtypes = [vp, vp]
     L.fm_plan_tune.argtypes = [vp, vp, vp]
     L.fm_plan_tiling.argtypes = [vp, ip, ip, ip]
+    L.fm_plan_set_tiling.argtypes = [vp, ip, ip, vp]
     L.fm_plan_device_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
     L.fm_server_create.argtypes = [ctypes.POINTER(vp), ctypes.c_size_t, ctypes.c_size_t, ctypes.c_int,
                                    ctypes.c_int]
     L.fm_server_submit.argtypes = [vp, ip, dp, ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                   ctypes.c_int, vp, vp, ctypes.POINTER(ctypes.c_longlong)]
-    L.fm_server_progress.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.c_int,
+                                   ctypes.c_int, vp, vp, vp, ctypes.POINTER(ctypes.c_longlong)]
+    L.fm_server_progress.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ip, ctypes.c_int,
                                      ctypes.POINTER(ctypes.c_int)]
     L.fm_server_wait_all.argtypes = [vp]
     L.fm_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
@@ -229,6 +230,13 @@ class Plan:
         _check(library().fm_plan_tiling(self._h, b, t, q), "fm_plan_tiling")
         return {"lines_per_tile": list(b), "tiles": list(t), "persistent": list(q)}
 
+    def set_tiling(self, lines_per_tile, persistent, stream=None):
+        """Apply a tiling as tiling() reports it (fm_plan_set_tiling)."""
+        b = (ctypes.c_int * 5)(*[int(v) for v in lines_per_tile])
+        q = (ctypes.c_int * 5)(*[int(v) for v in persistent])
+        _check(library().fm_plan_set_tiling(self._h, b, q, _stream_ptr(stream)), "fm_plan_set_tiling")
+        return self.tiling()
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             library().fm_plan_destroy(self._h)
@@ -319,9 +327,11 @@ class Server:
                "fm_server_create")
         self._h = handle
         self._keep = {}  # ticket -> (rhs, out): alive until finished
+        self.failed = {}  # ticket -> status of requests that finished with an error
 
-    def submit(self, n, h, bc, layout, rhs, out, prec=F32, green=CHAT2, kind=POISSON, ncomp=1):
-        """Enqueue one solve; returns its ticket."""
+    def submit(self, n, h, bc, layout, rhs, out, prec=F32, green=CHAT2, kind=POISSON, ncomp=1, stream=None):
+        """Enqueue one solve; returns its ticket.  The solve runs after the work enqueued
+        so far on `stream` (default: torch's current stream), which produced rhs."""
         import torch
         dt = torch.float64 if prec == F64 else torch.float32
         for t, name in ((rhs, "rhs"), (out, "out")):
@@ -331,18 +341,23 @@ class Server:
         ticket = ctypes.c_longlong()
         _check(library().fm_server_submit(self._h, n3, h3, b6, layout, green, prec, kind, ncomp,
                                           ctypes.c_void_p(rhs.data_ptr()), ctypes.c_void_p(out.data_ptr()),
-                                          ctypes.byref(ticket)), "fm_server_submit")
+                                          _stream_ptr(stream), ctypes.byref(ticket)), "fm_server_submit")
         self._keep[ticket.value] = (rhs, out)
         return ticket.value
 
     def progress(self, max_finished=4096):
-        """Admit and retire; returns the tickets finished since the last call."""
+        """Admit and retire; returns the tickets finished since the last call (those that
+        finished with an error are also entered in self.failed with their status)."""
         buf = (ctypes.c_longlong * max_finished)()
+        st = (ctypes.c_int * max_finished)()
         n = ctypes.c_int()
-        _check(library().fm_server_progress(self._h, buf, max_finished, ctypes.byref(n)), "fm_server_progress")
+        _check(library().fm_server_progress(self._h, buf, st, max_finished, ctypes.byref(n)),
+               "fm_server_progress")
         done = list(buf[:n.value])
-        for t in done:
+        for t, status in zip(done, st[:n.value]):
             self._keep.pop(t, None)
+            if status != 0:
+                self.failed[t] = status
         return done
 
     def wait_all(self):

@@ -68,3 +68,60 @@ def test_biot_savart_tubes_512_fp32_matches_fp64():
     print(f"tubes 512^3 FP32 vs FP64 rel_linf {err:.2e}")
     assert err < TOL32, err
     assert np.all(np.isfinite(u64))
+
+
+_TUNED_512 = {}
+
+
+def _tuned_512_tiling(prec):
+    """The tiling fm_plan_tune picks for the Biot-Savart 512^3 plan (the one bench.py
+    times), per precision."""
+    if prec not in _TUNED_512:
+        import torch
+        plan = F.Plan([512] * 3, [2 / 512] * 3, [[3, 3]] * 3, F.CELL, F.CHAT2, prec, F.BIOT_SAVART, 3)
+        _TUNED_512[prec] = plan.tune()
+        plan.close()
+        torch.cuda.empty_cache()
+    return _TUNED_512[prec]
+
+
+@pytest.mark.parametrize("prec,tol", [(F.F32, TOL32), (F.F64, TOL64)])
+@pytest.mark.parametrize("long_axis", [0, 1, 2])
+def test_biot_savart_1024_lines_against_oracle(long_axis, prec, tol):
+    """The kernels of the 512^3 Biot-Savart solve, against the oracle: one axis of 512
+    cells (FFT length 1024, as every axis at 512^3) and two short ones.  The passes along
+    the long axis run in the launch mode the tuner picks at 512^3, with as many lines per
+    tile as the short axes allow; along z this is the fused curl pass (in FP64 the long
+    runtime-length class, as at 512^3), along x the first and last passes, along y the
+    second and fourth."""
+    n = [6, 6, 6]
+    n[long_axis] = 512
+    h = [2 / 512] * 3
+    bc = [[3, 3]] * 3
+    tuned = _tuned_512_tiling(prec)
+    passes = {0: (0, 4), 1: (1, 3), 2: (2,)}[long_axis]
+    plan = F.Plan(n, h, bc, F.CELL, F.CHAT2, prec, F.BIOT_SAVART, 3)
+    t = plan.tiling()
+    for i in passes:
+        want_mode = tuned["persistent"][i]
+        for b in range(tuned["lines_per_tile"][i], 0, -1):
+            lines = list(t["lines_per_tile"])
+            modes = list(t["persistent"])
+            lines[i], modes[i] = b, want_mode
+            try:
+                t = plan.set_tiling(lines, modes)
+                break
+            except F.FluxmiError:
+                continue
+        assert t["persistent"][i] == want_mode, (i, t, tuned)
+    rng = np.random.default_rng(1024 + long_axis)
+    f = rng.standard_normal((3,) + O.user_shape(n, O.CELL))
+    import torch
+    x = torch.from_numpy(f).to("cuda", plan.dtype)
+    u = plan.solve(x)
+    torch.cuda.synchronize()
+    ref = O.solve(f, n, h, bc, O.CELL, 0, 1)
+    err = rel_linf(u.double().cpu().numpy(), ref)
+    print(f"Biot-Savart n={n} prec={prec} tiling={t} rel_linf={err:.2e}")
+    plan.close()
+    assert err < tol, err

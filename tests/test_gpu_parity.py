@@ -121,6 +121,20 @@ def test_edge_sizes_and_lengths():
         assert err < TOL32, (n, bc, err)
 
 
+def test_fp32_fused_real_to_real_length_32_runs_the_runtime_length_kernel():
+    """Every axis symmetric, the last (fused) one of FFT length 32 (16 cells, DCT-II):
+    FP32 plans run this pass in the runtime-length kernel (launch mode 2), against the
+    oracle in both layouts' cell form and with a ragged tile."""
+    for bc in ([[0, 0], [1, 0], [0, 0]], [[1, 1], [0, 1], [1, 1]]):
+        n = [6, 7, 16]
+        plan = F.Plan(n, [0.1, 0.12, 0.09], bc, F.CELL, F.CHAT2, F.F32)
+        assert plan.tiling()["persistent"][2] == 2
+        f = W.random_field(O.user_shape(n, F.CELL), 77)
+        err = rel_linf(gpu_solve(plan, f), oracle_solve(f, n, [0.1, 0.12, 0.09], bc, F.CELL))
+        plan.close()
+        assert err < TOL32, (bc, err)
+
+
 def test_errors_are_reported():
     with pytest.raises(F.FluxmiError):
         F.Plan([8, 8, 8], [0.1] * 3, [[2, 3], [3, 3], [3, 3]], F.CELL)

@@ -26,8 +26,8 @@ def test_served_results_equal_alone_and_oracle():
         assert f.shape == _shape(r)
         rhs.append(torch.from_numpy(f).to("cuda", torch.float32))
         outs.append(torch.full(f.shape, float("nan"), dtype=torch.float32, device="cuda"))
-    # cold pass: every plan is created (plan creation synchronises); a generous plan
-    # budget keeps them all for the warm pass
+    # cold pass: every plan is created (generated on the server's stream, each solve
+    # ordered after its plan); a generous plan budget keeps them all for the warm pass
     server = F.Server(workspace_budget_bytes=96 << 20, plan_budget_bytes=1 << 30, slots=6)
     tickets = [server.submit(r["n"], r["h"], r["bc"], r["layout"], x, o) for r, x, o in zip(reqs, rhs, outs)]
     finished = list(server.progress())
@@ -118,3 +118,67 @@ def test_serving_distribution_sample_matches_oracle():
         err = rel_linf(o.double().cpu().numpy(), ref)
         print("request", r["n"], r["bc"], r["layout"], f"rel_linf={err:.2e}")
         assert err < TOL32, (r, err)
+
+
+def test_requests_wait_for_their_producer_stream():
+    """Warm-plan requests submitted right after an asynchronous fill of their right-hand
+    sides on another stream, with no host synchronisation: each solve must see the filled
+    input (its submission recorded the producer stream)."""
+    import torch
+    reqs = W.serving_stream(count=12, qps=1e4, seed=34, edges=(32, 48))
+    server = F.Server(workspace_budget_bytes=64 << 20, plan_budget_bytes=1 << 30, slots=4)
+    fields = [torch.from_numpy(W.request_rhs(r)).to("cuda", torch.float32) for r in reqs]
+    rhs = [torch.zeros_like(f) for f in fields]
+    outs = [torch.empty_like(f) for f in fields]
+    for r, x, o in zip(reqs, rhs, outs):  # plans cached
+        server.submit(r["n"], r["h"], r["bc"], r["layout"], x, o)
+    server.wait_all()
+    server.progress()
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    a = torch.randn(2048, 2048, device="cuda")
+    with torch.cuda.stream(side):
+        for r, x, f, o in zip(reqs, rhs, fields, outs):
+            for _ in range(4):
+                a = a @ a / 64.0  # keeps the stream busy before the fill
+            x.copy_(f)
+            server.submit(r["n"], r["h"], r["bc"], r["layout"], x, o, stream=side)
+    server.wait_all()
+    server.progress()
+    torch.cuda.synchronize()
+    for r, f, o in zip(reqs, fields, outs):
+        p = F.Plan(r["n"], r["h"], r["bc"], r["layout"], F.CHAT2, F.F32)
+        assert torch.equal(p.solve(f), o), r
+        p.close()
+    server.close()
+
+
+def test_a_failed_request_is_reported_finished_with_its_error(monkeypatch):
+    """The error path of a request, forced from the host: the admission of one ticket is
+    made to fail before anything is enqueued; that ticket finishes with FM_E_HIP, the
+    others run, and wait_all returns."""
+    import torch
+    monkeypatch.setenv("FLUXMI_SERVER_FAIL_TICKET", "3")
+    reqs = W.serving_stream(count=6, qps=1e4, seed=35, edges=(32,))
+    server = F.Server(workspace_budget_bytes=64 << 20, plan_budget_bytes=1 << 30, slots=2)
+    work, tickets = [], []
+    for r in reqs:
+        x = torch.from_numpy(W.request_rhs(r)).to("cuda", torch.float32)
+        o = torch.full_like(x, float("nan"))
+        tickets.append(server.submit(r["n"], r["h"], r["bc"], r["layout"], x, o))
+        work.append((r, x, o))
+    done = server.progress()
+    server.wait_all()
+    done += server.progress()
+    assert sorted(done) == sorted(tickets)
+    assert server.failed == {3: -6}
+    st = server.stats()
+    assert st["finished"] == len(reqs) and st["failed"] == 1
+    for t, (r, x, o) in zip(tickets, work):
+        if t == 3:
+            assert torch.isnan(o).all()
+            continue
+        p = F.Plan(r["n"], r["h"], r["bc"], r["layout"], F.CHAT2, F.F32)
+        assert torch.equal(p.solve(x), o)
+        p.close()
+    server.close()
