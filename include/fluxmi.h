@@ -69,6 +69,11 @@ typedef enum { FM_POISSON = 0, FM_BIOT_SAVART = 1 } fm_kind;
 #define FM_E_NOMEM (-5)  /* device allocation failed                                 */
 #define FM_E_HIP (-6)    /* a HIP call failed; fm_last_hip_error() has its code      */
 #define FM_E_ARG (-7)    /* inconsistent arguments (count, workspace too small, ...) */
+#define FM_E_SCRATCH (-8) /* fm_solve_static: the plan's workspace exceeds
+                             FM_STATIC_WORKSPACE_BYTES                                */
+
+/* Size of the library's fixed device workspace used by fm_solve_static. */
+#define FM_STATIC_WORKSPACE_BYTES ((size_t)128 << 20)
 
 typedef struct fm_plan_s* fm_plan;
 
@@ -115,6 +120,20 @@ int fm_plan_shape(fm_plan p, int user_dims[3]);
  * values at those positions are ignored.
  * Errors: FM_E_NULL, FM_E_NOMEM (the plan's own workspace), FM_E_HIP (a launch). */
 int fm_solve(fm_plan p, const void* rhs_dev, void* out_dev, void* workspace_dev, void* hip_stream);
+
+/* fm_solve for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the workspace is a
+ * fixed device array of the library, FM_STATIC_WORKSPACE_BYTES (128 MiB) per GPU, held
+ * from the library's load until the process ends.  The call allocates nothing (no
+ * hipMalloc, no allocating library routine); rhs_dev and out_dev are the caller's, as
+ * for fm_solve, and the results are those of fm_solve with the same plan.
+ * Every call on one GPU uses that GPU's one array, which keeps the last call's
+ * contents: calls that overlap on one GPU (other streams, other host threads) race and
+ * must be serialised by the caller.
+ * Errors: FM_E_NULL; FM_E_SCRATCH if fm_plan_workspace_bytes exceeds
+ * FM_STATIC_WORKSPACE_BYTES (e.g. FP32 fully unbounded grids beyond about 180^3);
+ * FM_E_HIP (symbol lookup or launch). */
+int fm_solve_static(fm_plan p, const void* rhs_dev, void* out_dev, void* hip_stream);
 
 /* Run passes [first_pass, last_pass] (0-based, of the five: 0 first-axis forward,
  * 1 second-axis forward, 2 last-axis forward + spectral multiply + inverse,

@@ -38,11 +38,13 @@ def _units():
     units.append((os.path.join(CSRC, "fm_gen.hip"), "gen.o", []))
     units.append((os.path.join(CSRC, "fm_plan.cpp"), "plan.o", []))
     units.append((os.path.join(CSRC, "fm_serve.cpp"), "serve.o", []))
+    units.append((os.path.join(CSRC, "fm_static.hip"), "static.o", []))
     return units
 
 
 def _sources():
-    return [os.path.join(CSRC, f) for f in ("fm_inst.hip", "fm_gen.hip", "fm_plan.cpp", "fm_serve.cpp")] + \
+    return [os.path.join(CSRC, f) for f in ("fm_inst.hip", "fm_gen.hip", "fm_plan.cpp", "fm_serve.cpp",
+                                            "fm_static.hip")] + \
         [os.path.join(CSRC, h) for h in HEADERS] + [os.path.join(os.path.dirname(HERE), "include", "fluxmi.h")]
 
 

@@ -1231,6 +1231,7 @@ const char* fm_error_string(int status) {
     case FM_E_NOMEM: return "device allocation failed";
     case FM_E_HIP: return "HIP runtime error";
     case FM_E_ARG: return "inconsistent arguments";
+    case FM_E_SCRATCH: return "workspace exceeds the static scratch of fm_solve_static (FM_STATIC_WORKSPACE_BYTES)";
     default: return "unknown status";
   }
 }

@@ -26,8 +26,9 @@ EXPORTED = [
     "fm_error_string", "fm_last_hip_error", "fm_batch_prepare", "fm_batch_run", "fm_batch_destroy",
     "fm_plan_tune", "fm_plan_tiling", "fm_plan_device_bytes",
     "fm_server_create", "fm_server_submit", "fm_server_progress", "fm_server_wait_all",
-    "fm_server_get_stats", "fm_server_destroy", "fm_plan_set_tiling",
+    "fm_server_get_stats", "fm_server_destroy", "fm_solve_static", "fm_plan_set_tiling",
 ]
+STATIC_WORKSPACE_BYTES = 128 << 20  # FM_STATIC_WORKSPACE_BYTES
 
 
 class ServerStats(ctypes.Structure):
@@ -81,6 +82,7 @@ def library():
     L.fm_plan_shape.argtypes = [vp, ip]
     L.fm_solve.argtypes = [vp, vp, vp, vp, vp]
     L.fm_solve_passes.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_int, vp]
+    L.fm_solve_static.argtypes = [vp, vp, vp, vp]
     L.fm_solve_batched.argtypes = [ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                    ctypes.POINTER(vp), vp, ctypes.c_size_t, vp]
     L.fm_batched_workspace_bytes.argtypes = [ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_size_t)]
@@ -203,6 +205,16 @@ class Plan:
             ws = ctypes.c_void_p(workspace.data_ptr())
         _check(library().fm_solve(self._h, ctypes.c_void_p(rhs.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                   ws, _stream_ptr(stream)), "fm_solve")
+        return out
+
+    def solve_static(self, rhs, out, stream=None):
+        """fm_solve_static: a solve whose workspace is the library's fixed device array
+        (no allocation in the call; calls on one GPU must not overlap)."""
+        self._check_tensor(rhs, "rhs")
+        self._check_tensor(out, "out")
+        _check(library().fm_solve_static(self._h, ctypes.c_void_p(rhs.data_ptr()),
+                                         ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)),
+               "fm_solve_static")
         return out
 
     def solve_passes(self, rhs, out, first, last, workspace=None, stream=None):

@@ -25,7 +25,7 @@ def test_exports_every_declared_symbol():
 
 
 def test_error_strings():
-    for code in range(-7, 1):
+    for code in range(-8, 1):
         assert F.error_string(code)
 
 
