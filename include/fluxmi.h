@@ -146,8 +146,9 @@ int fm_solve_passes(fm_plan p, const void* rhs_dev, void* out_dev, void* workspa
 
 /* Solve `count` independent problems (plans may differ in shape, boundary conditions
  * and layout, but must share one precision).  FP64 batches run with one launch per pass
- * and length class for the whole batch; FP32 batches run plan by plan with the
- * single-solve kernels.  Each result is bitwise identical to fm_solve of the same plan.
+ * and length class for the whole batch, except fused passes in the per-wavefront kernel
+ * (fm_plan_tiling mode 3), which are launched plan by plan; FP32 batches run plan by plan
+ * with the single-solve kernels.  Each result is bitwise identical to fm_solve of the same plan.
  *   workspace_dev  at least fm_batched_workspace_bytes(count, plans) bytes
  * Errors: FM_E_ARG if the plans mix precisions or the workspace is too small, FM_E_NULL
  * for a null plan array, buffer array or buffer. */
@@ -171,7 +172,10 @@ int fm_plan_device_bytes(fm_plan p, size_t* bytes);
 
 /* The plan's current tiling per pass: lines per tile, tiles, and the launch mode
  * persist[i]: 1 persistent grid (twiddle tables in LDS), 0 one tile per workgroup with
- * the tables in LDS, 2 one tile per workgroup with the tables read from global memory. */
+ * the tables in LDS, 2 one tile per workgroup with the tables read from global memory,
+ * 3 the per-wavefront fused kernel (complex lines of a power-of-two length from 32 to
+ * 1024 along the last axis: each 64-lane wavefront transforms, multiplies and inverts
+ * whole lines in registers; lines_per_tile is then the lines of one workgroup). */
 int fm_plan_tiling(fm_plan p, int lines_per_tile[5], int tiles[5], int persist[5]);
 
 /* Set the tiling of every pass, as fm_plan_tiling reports it (for example a tiling that

@@ -5,6 +5,7 @@
 
 #include "fm_device.h"
 #include "fm_launch.h"
+#include "fm_wave.h"
 
 #ifndef FM_T
 #error "FM_T must be defined"
@@ -23,9 +24,35 @@ static hipError_t allow_full_lds() {
   return once;
 }
 
+// Fused complex passes in the per-wavefront kernel: d.B / wave_lines(M) wavefronts per
+// workgroup, one workgroup per tile.  FP64 three-component (curl) lines would hold 48
+// complex doubles per lane and are not built.
+template <int KIND>
+static hipError_t launch_wave(const PassDesc& d, const PassDesc* dev, const void* in, void* out,
+                              hipStream_t st) {
+  if constexpr (wave_length(FM_MC) &&
+                (KIND == K_F_C2C || (KIND == K_F_CURL && sizeof(FM_T) == 4))) {
+    const int threads = 64 * (d.B / wave_lines(FM_MC));
+    if (threads < 64 || threads > kThreads) return hipErrorInvalidValue;
+    if (d.lds_bytes > kSoftLds) {
+      const hipError_t e = allow_full_lds<&wave_pass_kernel<FM_T, FM_MC, KIND>>();
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((wave_pass_kernel<FM_T, FM_MC, KIND>), dim3(d.tiles), dim3(threads), d.lds_bytes,
+                       st, dev, in, out);
+    return hipGetLastError();
+  } else {
+    (void)d; (void)dev; (void)in; (void)out; (void)st;
+    return hipErrorInvalidValue;
+  }
+}
+
 template <int KIND>
 static hipError_t launch_kind(const PassDesc& d, const PassDesc* dev, const void* in, void* out,
                               hipStream_t st) {
+  if constexpr (KIND == K_F_C2C || KIND == K_F_CURL) {
+    if (d.wave) return launch_wave<KIND>(d, dev, in, out, st);
+  }
   static const bool persistent = [] {
     const char* e = std::getenv("FLUXMI_PERSISTENT");
     return e == nullptr || std::atoi(e) != 0;

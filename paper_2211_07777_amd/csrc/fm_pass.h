@@ -135,6 +135,40 @@ constexpr int radix_at(int M, int s, int rmax) {
 // LDS banks; lines are fft_line_stride(M) slots apart.
 constexpr int fft_line_stride(int M) { return M + (M >> 4) + 1; }
 
+// Per-wavefront fused kernels (complex lines of a power-of-two length M, 32 <= M <= 1024):
+// each lane holds kWaveValues points of a line, so a line spans P = M / kWaveValues
+// lanes.  Radix schedule: kWaveValues first, then min(kWaveValues, rest) until the
+// product is M.  Stage s >= 1 reads its twiddles W_{Ns R}^{k r} (Ns = product of the
+// earlier radices, 1 <= r < R, k < Ns) from a table at wave_tw_offset(M, s) + (r-1) Ns + k.
+constexpr int kWaveValues = 16;
+constexpr bool wave_length(int M) {
+  return M >= 2 * kWaveValues && M <= 64 * kWaveValues && (M & (M - 1)) == 0;
+}
+constexpr int wave_radix(int M, int s) {
+  int rest = M / kWaveValues;
+  if (s == 0) return kWaveValues;
+  for (int i = 1; i < s; ++i) rest /= (rest < kWaveValues ? rest : kWaveValues);
+  return rest <= 1 ? 0 : (rest < kWaveValues ? rest : kWaveValues);
+}
+constexpr int wave_ns(int M, int s) {
+  int n = 1;
+  for (int i = 0; i < s; ++i) n *= wave_radix(M, i);
+  return n;
+}
+constexpr int wave_tw_offset(int M, int s) {
+  int off = 0;
+  for (int i = 1; i < s; ++i) off += wave_ns(M, i) * (wave_radix(M, i) - 1);
+  return off;
+}
+constexpr int wave_stage_count(int M) {
+  int s = 0;
+  while (wave_radix(M, s) != 0) ++s;
+  return s;
+}
+constexpr int wave_tw_size(int M) { return wave_tw_offset(M, wave_stage_count(M)); }
+// lines one wavefront holds (0 for lengths the per-wavefront kernels do not serve)
+constexpr int wave_lines(int M) { return wave_length(M) ? 64 / (M / kWaveValues) : 0; }
+
 // Lengths with compile-time kernels (other lengths use the runtime-length kernel).
 constexpr int kFastLens[] = {32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 2048, 4096};
 
@@ -207,6 +241,9 @@ struct PassDesc {
   int32_t lds_tabs;         // compile-time-length kernels that allow it: 1 = twiddle tables
                             // staged in LDS (persistent loop, or one tile per workgroup);
                             // 0 = one tile per workgroup reading them from global memory
+  int32_t wave;             // fused complex pass in the per-wavefront kernel (fm_wave.h):
+                            // B = lines per workgroup, a multiple of wave_lines(M)
+  const void* wtw;          // its stage twiddle table (wave_tw_size(M) entries)
 };
 
 // Sampling description of the Green's function for the spectrum generation (FP64).

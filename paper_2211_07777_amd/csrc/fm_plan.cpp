@@ -27,6 +27,7 @@ hipError_t launch_pass_batched(int len_class, const PassDesc* ds, const int* pre
                                int total_tiles, int lds_bytes, hipStream_t st);
 template <typename T> hipError_t launch_twiddles(void* out, int M, hipStream_t st);
 template <typename T> hipError_t launch_stage_twiddles(void* out, int M, hipStream_t st);
+template <typename T> hipError_t launch_wave_twiddles(void* out, int M, hipStream_t st);
 bool is_fast_len(int M);
 
 hipError_t launch_green_sample(double* S, const GreenGen& g, hipStream_t st);
@@ -251,6 +252,7 @@ struct fm_plan_s {
   std::map<int, void*> tw;
   std::map<int, void*> stw;
   std::map<int, void*> tw64;
+  std::map<int, void*> wtw;  // stage twiddles of the per-wavefront kernels
   void* ws_internal = nullptr;
   std::mutex ws_mu;  // guards the lazy allocation of ws_internal
   // Deferred creation (serving loop): the generation kernels may still run when the
@@ -381,6 +383,39 @@ int choose_tile(fm::PassDesc* d, size_t elem, int comps, bool fused_r2r, int nb,
   return FM_E_SIZE;
 }
 
+// The per-wavefront fused kernel (fm_wave.h): complex fused passes of a power-of-two
+// length whose lines are contiguous in memory (every fused complex pass: the last axis
+// is the fastest of its layout); three-component lines in FP32 only.
+bool wave_capable(const fm::PassDesc& d, size_t elem) {
+  if (!d.fused || d.gather != fm::G_CPLX || d.long_rt || !fm::wave_length(d.M)) return false;
+  if (d.g.curl && elem != 4) return false;
+  return d.in_s_line == 1 && d.out_s_line == 1;
+}
+
+size_t wave_lds(int B, int M, size_t elem) {
+  return round256((size_t)B * fm::fft_line_stride(M) * 2 * elem);
+}
+
+// Pass d in the per-wavefront kernel with W (1, 2 or 4) wavefronts per workgroup; false
+// if it cannot run there.  comp_tiles: tiles per (b, c) tile position (ncomp, or 1 for
+// the three-component curl).
+bool set_wave(fm::PassDesc* d, size_t elem, int W, int comp_tiles) {
+  if (!wave_capable(*d, elem) || (W != 1 && W != 2 && W != 4)) return false;
+  const int B = W * fm::wave_lines(d->M);
+  const size_t lds = wave_lds(B, d->M, elem);
+  if (lds > (size_t)fm::kMaxLds) return false;
+  d->wave = 1;
+  d->B = B;
+  d->lds_bytes = (int)lds;
+  d->raw_off = d->g_off = d->tab_off = 0;
+  d->stw_n = d->tw_n = 0;
+  d->persist = 0;
+  d->lds_tabs = 0;
+  d->tiles = ((d->nb + B - 1) / B) * d->nc * comp_tiles;
+  set_magics(d);
+  return true;
+}
+
 // Fill the geometry of a pass: lines along `la`, tiles along `lb`, index `lc`.
 void set_geometry(fm::PassDesc* d, int la, int lb, int lc, const int64_t sin_[3], int64_t in_size,
                   const int64_t sout[3], int64_t out_size, const int ext_b[3]) {
@@ -470,6 +505,19 @@ int make_tables_and_green(fm_plan_s* p, hipStream_t st, bool deferred) {
       FM_HIP(fm::launch_stage_twiddles<T>(ptr, M, st));
     }
     p->pass[i].stw = p->stw[M];
+  }
+
+  // stage twiddles of the per-wavefront kernel (the fused pass may run there, now or
+  // after tuning)
+  if (wave_capable(p->pass[2], p->elem)) {
+    const int M = p->pass[2].M;
+    void* ptr = nullptr;
+    const size_t n = (size_t)std::max(1, fm::wave_tw_size(M));
+    if (hipMalloc(&ptr, sizeof(T) * 2 * n) != hipSuccess) return FM_E_NOMEM;
+    p->wtw[M] = ptr;
+    p->table_bytes += sizeof(T) * 2 * n;
+    FM_HIP(fm::launch_wave_twiddles<T>(ptr, M, st));
+    p->pass[2].wtw = ptr;
   }
 
   // Green's spectrum: sample (FP64) -> DCT-I along convolution directions -> scale
@@ -599,6 +647,7 @@ void free_plan(fm_plan_s* p) {
   release_generation(p);
   for (auto& kv : p->tw) (void)hipFree(kv.second);
   for (auto& kv : p->stw) (void)hipFree(kv.second);
+  for (auto& kv : p->wtw) (void)hipFree(kv.second);
   if (p->G) (void)hipFree(p->G);
   if (p->dpass) (void)hipFree(p->dpass);
   if (p->ws_internal) (void)hipFree(p->ws_internal);
@@ -636,9 +685,36 @@ int64_t tile_in_span_bytes(const fm::PassDesc& d, size_t elem) {
   return ((int64_t)(d.B - 1) * d.in_s_b + (int64_t)(d.in_n - 1) * d.in_s_line + 1) * es;
 }
 
+// Host-side check of a pass in the per-wavefront kernel: what wave_tile touches.
+bool wave_in_bounds(const fm::PassDesc& d, int64_t in_size, int64_t out_size, size_t elem) {
+  auto span = [](int nc, int64_t sc, int nb, int64_t sb, int n, int64_t sl) {
+    return (int64_t)(nc - 1) * sc + (int64_t)(nb - 1) * sb + (int64_t)(n - 1) * sl;
+  };
+  if (!wave_capable(d, elem) || d.has_fix) return false;
+  const int L = fm::wave_lines(d.M);
+  if (L < 1) return false;
+  const int W = d.B / L;
+  if (d.B % L || (W != 1 && W != 2 && W != 4)) return false;
+  if (d.nb < 1 || d.nc < 1 || d.in_n < 1 || d.out_n < 1) return false;
+  if (d.n_data < 0 || d.n_data > d.in_n || d.n_data > d.M || d.out_n > d.M) return false;
+  int prodR = 1;
+  for (int i = 0; i < d.nstages; ++i) prodR *= d.radix[i];
+  if (prodR != d.M) return false;
+  if (span(d.nc, d.in_s_c, d.nb, d.in_s_b, d.in_n, d.in_s_line) >= in_size) return false;
+  if (span(d.nc, d.out_s_c, d.nb, d.out_s_b, d.out_n, d.out_s_line) >= out_size) return false;
+  const int comps = d.g.curl ? 3 : d.ncomp;
+  if (d.g.curl && d.ncomp != 3) return false;
+  if (comps > 1 && (d.in_s_comp < in_size || d.out_s_comp < out_size)) return false;
+  if (d.g.fold_line != d.M || d.g.F_line < d.M / 2 + 1) return false;
+  if ((size_t)d.lds_bytes < wave_lds(d.B, d.M, elem) || d.lds_bytes > fm::kMaxLds) return false;
+  const int nbt = (d.nb + d.B - 1) / d.B;
+  return d.tiles == nbt * d.nc * (d.g.curl ? 1 : d.ncomp);
+}
+
 // Host-side check of one pass against the buffers and the LDS / register budgets; the
 // index ranges mirror what the tile kernels touch.
 bool pass_in_bounds(const fm::PassDesc& d, int64_t in_size, int64_t out_size, size_t elem) {
+  if (d.wave) return wave_in_bounds(d, in_size, out_size, elem);
   auto span = [](int nc, int64_t sc, int nb, int64_t sb, int n, int64_t sl) {
     return (int64_t)(nc - 1) * sc + (int64_t)(nb - 1) * sb + (int64_t)(n - 1) * sl;
   };
@@ -923,6 +999,17 @@ int build_plan(fm_plan_s* p) {
     if (rc2) return rc2;
     d.tiles = ((d.nb + d.B - 1) / d.B) * d.nc * (fused_curl ? 1 : p->ncomp);
     set_magics(&d);
+    if (i == 2 && wave_capable(d, p->elem)) {
+      // the per-wavefront kernel, with the most wavefronts per workgroup whose LDS stays
+      // within the preferred size
+      for (const int W : {4, 2, 1}) {
+        fm::PassDesc w = d;
+        if (set_wave(&w, p->elem, W, fused_curl ? 1 : p->ncomp) && w.lds_bytes <= fm::kSoftLds) {
+          d = w;
+          break;
+        }
+      }
+    }
   }
   for (int i = 0; i < 5; ++i) p->pass[i].kind = pass_kind(p->pass[i]);
   const int64_t sizes_in[5] = {p->Vu, p->V1, p->V2, p->V2, p->V1};
@@ -1001,8 +1088,10 @@ struct fm_batch_s {
   struct Group {
     int pass, len_class, first, count, tiles, lds;
     size_t off_desc, off_pref;
+    int single;  // >= 0: one per-wavefront pass, launched alone (host copy singles[single])
   };
   std::vector<Group> groups;
+  std::vector<fm::PassDesc> singles;
   char* dev_tables = nullptr;
   // prepared FP32 batches: the plans are spread over these streams (default priority),
   // forked from and joined back into the caller's stream with events
@@ -1062,6 +1151,12 @@ int build_batch(int count, const fm_plan* plans, const void* const* rhs_dev, voi
     std::map<int, std::vector<int>> by_class;
     for (int i = 0; i < count; ++i) {
       const fm::PassDesc& d = all[5 * (size_t)i + ps];
+      // passes in the per-wavefront kernel keep it (the batch equals the single solves
+      // bitwise) and are launched one by one; their class key is unique and negative
+      if (d.wave) {
+        by_class[-1 - i].push_back(i);
+        continue;
+      }
       const int rt = (d.M > fm::kMaxFastLen64 || d.long_rt) ? fm::kRtLong : fm::kRtShort;
       by_class[d.stw ? d.M : rt].push_back(i);
     }
@@ -1069,6 +1164,11 @@ int build_batch(int count, const fm_plan* plans, const void* const* rhs_dev, voi
       fm_batch_s::Group g{};
       g.pass = ps;
       g.len_class = kv.first;
+      g.single = -1;
+      if (kv.first < 0) {
+        g.single = (int)b->singles.size();
+        b->singles.push_back(all[5 * (size_t)kv.second[0] + ps]);
+      }
       g.first = (int)order.size();
       g.count = (int)kv.second.size();
       for (int i : kv.second) order.push_back(i);
@@ -1128,7 +1228,13 @@ int run_batch(const fm_batch_s& b, hipStream_t st) {
   for (const fm_batch_s::Group& g : b.groups) {
     const fm::PassDesc* dd = reinterpret_cast<const fm::PassDesc*>(b.dev_tables + g.off_desc);
     const int* dp = reinterpret_cast<const int*>(b.dev_tables + g.off_pref);
-    hipError_t e = fm::launch_pass_batched<double>(g.len_class, dd, dp, g.count, g.tiles, g.lds, st);
+    hipError_t e;
+    if (g.single >= 0) {
+      const fm::PassDesc& h = b.singles[g.single];
+      e = fm::launch_pass<double>(h, dd, h.in, h.out, st);
+    } else {
+      e = fm::launch_pass_batched<double>(g.len_class, dd, dp, g.count, g.tiles, g.lds, st);
+    }
     if (e != hipSuccess) {
       g_last_hip = (int)e;
       return FM_E_HIP;
@@ -1374,6 +1480,7 @@ int fm_solve_batched(int count, const fm_plan* plans, const void* const* rhs_dev
 // tables, 0 one tile per workgroup with LDS tables, 2 one tile per workgroup with global
 // tables (the only mode of the runtime-length and long FP64 kernels).
 int launch_mode(const fm::PassDesc& d, size_t elem) {
+  if (d.wave) return 3;
   const bool pipelined = compile_time_kernel(d, elem) && fm::pipelined_kernel((int)elem, d.M);
   if (!pipelined || !d.lds_tabs) return 2;
   return d.persist ? 1 : 0;
@@ -1386,6 +1493,21 @@ int launch_mode(const fm::PassDesc& d, size_t elem) {
 bool retile(const fm_plan_s* p, int i, int bmax, int mode, fm::PassDesc* out) {
   fm::PassDesc d = p->pass[i];
   const bool fused_curl = (i == 2) && p->kind == FM_BIOT_SAVART;
+  const int64_t sizes_in[5] = {p->Vu, p->V1, p->V2, p->V2, p->V1};
+  const int64_t sizes_out[5] = {p->V1, p->V2, p->V2, p->V1, p->Vu};
+  d.wave = 0;
+  if (mode == 3) {
+    // the per-wavefront kernel: the most wavefronts per workgroup within bmax lines
+    if (!wave_capable(d, p->elem)) return false;
+    for (const int W : {4, 2, 1}) {
+      fm::PassDesc w = d;
+      if (W * fm::wave_lines(d.M) > bmax || !set_wave(&w, p->elem, W, fused_curl ? 1 : p->ncomp)) continue;
+      if (!pass_in_bounds(w, sizes_in[i], sizes_out[i], p->elem)) return false;
+      *out = w;
+      return true;
+    }
+    return false;
+  }
   d.persist = mode == 1;
   d.lds_tabs = mode != 2;
   if (choose_tile(&d, p->elem, fused_curl ? 3 : 1, (i == 2) && d.gather == fm::G_R2R, d.nb, bmax))
@@ -1393,8 +1515,6 @@ bool retile(const fm_plan_s* p, int i, int bmax, int mode, fm::PassDesc* out) {
   d.tiles = ((d.nb + d.B - 1) / d.B) * d.nc * (fused_curl ? 1 : p->ncomp);
   set_magics(&d);
   if (d.stw && tile_in_span_bytes(d, p->elem) >= (int64_t(1) << 32)) return false;
-  const int64_t sizes_in[5] = {p->Vu, p->V1, p->V2, p->V2, p->V1};
-  const int64_t sizes_out[5] = {p->V1, p->V2, p->V2, p->V1, p->Vu};
   if (!pass_in_bounds(d, sizes_in[i], sizes_out[i], p->elem)) return false;
   *out = d;
   return true;
@@ -1448,7 +1568,7 @@ int fm_plan_tune(fm_plan p, void* workspace_dev, void* hip_stream) {
     he = time_pass(i, best, &best_ms);
     std::vector<std::pair<int, int>> seen{{best.B, launch_mode(best, p->elem)}};
     for (const int bmax : {64, 32, 16, 8, 4, 2, 1}) {
-      for (const int mode : {1, 0, 2}) {
+      for (const int mode : {1, 0, 2, 3}) {
         fm::PassDesc d;
         if (he != hipSuccess || !retile(p, i, bmax, mode, &d)) continue;
         const std::pair<int, int> key{d.B, launch_mode(d, p->elem)};
@@ -1499,7 +1619,7 @@ int fm_plan_set_tiling(fm_plan p, const int lines_per_tile[5], const int persist
   fm::PassDesc next[5];
   for (int i = 0; i < 5; ++i) {
     const int mode = persist[i];
-    if (lines_per_tile[i] < 1 || mode < 0 || mode > 2) return FM_E_ARG;
+    if (lines_per_tile[i] < 1 || mode < 0 || mode > 3) return FM_E_ARG;
     if (!retile(p, i, lines_per_tile[i], mode, &next[i])) return FM_E_ARG;
     // exactly the requested tiling (retile takes the largest tile up to the bound)
     if (next[i].B != lines_per_tile[i] || launch_mode(next[i], p->elem) != mode) return FM_E_ARG;

@@ -184,3 +184,46 @@ def test_batched_bitwise_equals_single(prec):
     torch.cuda.synchronize()
     for s, o in zip(singles, outs):
         assert torch.equal(s, o)
+
+
+@pytest.mark.parametrize("prec,tol", [(F.F64, TOL64), (F.F32, TOL32)])
+@pytest.mark.parametrize("M", [32, 64, 128, 256, 512, 1024])
+def test_per_wavefront_fused_kernel(M, prec, tol):
+    """The per-wavefront fused kernel (launch mode 3) at every power-of-two line length it
+    serves, with 1, 2 and 4 wavefronts per workgroup (ragged last tiles): unbounded and
+    periodic last axes, both layouts, two right-hand sides per solve, and the spectral
+    curl (FP32)."""
+    rng = np.random.default_rng(M + 7 * prec)
+    cases = [([6, 5, M // 2], [[3, 3], [0, 1], [3, 3]], F.CELL, F.POISSON, 2),
+             ([7, 6, M // 2], [[1, 3], [2, 2], [3, 3]], F.NODE, F.POISSON, 1),
+             ([5, 6, M], [[2, 2], [1, 0], [2, 2]], F.NODE, F.POISSON, 1)]
+    if prec == F.F32:
+        cases.append(([6, 5, M // 2], [[3, 3], [2, 2], [3, 3]], F.CELL, F.BIOT_SAVART, 3))
+        cases.append(([5, 6, M], [[2, 2], [2, 2], [2, 2]], F.NODE, F.BIOT_SAVART, 3))
+    h = [0.11, 0.09, 1.0 / M]
+    for n, bc, layout, kind, ncomp in cases:
+        plan = F.Plan(n, h, bc, layout, F.CHAT2, prec, kind, ncomp)
+        t = plan.tiling()
+        assert t["persistent"][2] == 3, (n, bc, t)
+        lines = 64 // (M // 16)
+        shape = ((ncomp,) if ncomp > 1 else ()) + O.user_shape(n, layout)
+        f = rng.standard_normal(shape)
+        if kind == F.BIOT_SAVART:
+            ref = oracle_solve(f, n, h, bc, layout, 0, 1)
+        else:
+            ref = np.stack([oracle_solve(f[c] if ncomp > 1 else f, n, h, bc, layout) for c in range(ncomp)])
+            ref = ref if ncomp > 1 else ref[0]
+        for waves in (1, 2, 4):
+            b = list(t["lines_per_tile"])
+            q = list(t["persistent"])
+            b[2], q[2] = waves * lines, 3
+            try:
+                plan.set_tiling(b, q)
+            except F.FluxmiError:
+                assert prec == F.F64 and M * waves * lines * 16 > 160 * 1024, (M, waves)
+                continue
+            u = gpu_solve(plan, f)
+            check_conventions(u, bc, layout)
+            err = rel_linf(u, ref)
+            assert err < tol, (M, n, bc, layout, kind, waves, err)
+        plan.close()
