@@ -144,6 +144,26 @@ int fm_solve_static(fm_plan p, const void* rhs_dev, void* out_dev, void* hip_str
 int fm_solve_passes(fm_plan p, const void* rhs_dev, void* out_dev, void* workspace_dev,
                     int first_pass, int last_pass, void* hip_stream);
 
+/* The plain transforms of a plan, without the spectral multiplication: the forward
+ * operation of every axis chosen by its boundary conditions (DFT of the zero-padded
+ * data along unbounded axes, DFT along periodic axes, the DCT / DST of Table I along
+ * symmetric axes, the padded DCT / DST along semi-unbounded axes; Sec. II-B, II-C), and
+ * the backward operation with the crop and the output conventions of fm_solve.  Both
+ * are unnormalised (backward(forward(f)) = prod_a n_log,a * f, where n_log is N for a
+ * periodic axis, 2N for an unbounded or symmetric one and 4N for a semi-unbounded one).
+ * The first DFT axis in the plan's order holds the half spectrum (k <= M/2) of its
+ * real-to-complex transform.  The spectrum is laid out as fm_plan_spectrum_layout
+ * reports: [ncomp][dims[0]][dims[1]][dims[2]] (dims[2] fastest), where axes[i] is the
+ * physical axis (0 x, 1 y, 2 z) of dimension i, complex interleaved if is_complex, in the
+ * plan's precision; *bytes is its size.  This is the layout the solve works in (the last
+ * transformed axis fastest), so a forward transform costs three passes and moves no
+ * data twice.  rhs / out as for fm_solve; the workspace as for fm_solve (its contents
+ * do not carry over between the two calls).
+ * Errors: FM_E_NULL, FM_E_NOMEM (the plan's own workspace), FM_E_HIP. */
+int fm_plan_spectrum_layout(fm_plan p, int dims[3], int axes[3], int* is_complex, size_t* bytes);
+int fm_fft_forward(fm_plan p, const void* in_dev, void* spec_dev, void* workspace_dev, void* hip_stream);
+int fm_fft_backward(fm_plan p, const void* spec_dev, void* out_dev, void* workspace_dev, void* hip_stream);
+
 /* Solve `count` independent problems (plans may differ in shape, boundary conditions
  * and layout, but must share one precision).  FP64 batches run with one launch per pass
  * and length class for the whole batch, except fused passes in the per-wavefront kernel

@@ -64,7 +64,9 @@ def lib():
         L.oracle_green_spectrum.argtypes = [ip, dp, ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
         L.oracle_spectral_dims.argtypes = [ip, dp, ip, ctypes.c_int, ip]
         L.oracle_direct_points.argtypes = [ip, dp, ip, ctypes.c_int, ctypes.c_int, dp, ctypes.c_int, ip, dp]
+        L.oracle_transform.argtypes = [ip, dp, ip, ctypes.c_int, ctypes.c_int, dp, dp]
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_set_num_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
@@ -175,5 +177,32 @@ def green_spectrum(n, h, bc, layout, green=0, mode=FAST):
     return out
 
 
+def forward(f, n, h, bc, layout):
+    """Forward transforms of every axis (no spectral multiplication), unnormalised:
+    complex spectrum [sz][sy][sx], full length along every axis."""
+    n, h, bc = _prep(n, h, bc)
+    shp = user_shape(n, layout)
+    f = np.ascontiguousarray(f, dtype=np.float64).reshape(shp)
+    dx, dy, dz = spectral_dims(n, h, bc, layout)
+    out = np.empty((dz, dy, dx), dtype=np.complex128)
+    _check(lib().oracle_transform(_ip(n), _dp(h), _ip(bc), layout, -1, _dp(f), _dp(out.view(np.float64))))
+    return out
+
+
+def backward(F, n, h, bc, layout):
+    """Backward transforms of every axis with the crop and fix-ups, unnormalised: the real
+    part on the user grid [nz][ny][nx]."""
+    n, h, bc = _prep(n, h, bc)
+    F = np.ascontiguousarray(F, dtype=np.complex128)
+    out = np.empty(user_shape(n, layout))
+    _check(lib().oracle_transform(_ip(n), _dp(h), _ip(bc), layout, +1, _dp(F.view(np.float64)), _dp(out)))
+    return out
+
+
 def num_threads():
     return lib().oracle_num_threads()
+
+
+def set_num_threads(n):
+    """OpenMP threads of later oracle calls."""
+    lib().oracle_set_num_threads(int(n))

@@ -934,6 +934,32 @@ int oracle_direct_points(const int* n, const double* h, const int* bc, int layou
   return direct_points(P, rhs, npts, pts, out);
 }
 
+// The plain transforms of a plan without the spectral multiplication (Sec. II-B, II-C:
+// the forward operation of every axis, or the backward operation with its crop and
+// fix-ups), unnormalised.  dir -1: in = real user field [nz][ny][nx], out = complex
+// spectrum [sz][sy][sx] (interleaved, full length along every axis); dir +1: in =
+// complex spectrum, out = real part of the backward transform on the user grid.
+int oracle_transform(const int* n, const double* h, const int* bc, int layout, int dir,
+                     const double* in, double* out) {
+  Problem P;
+  const int rc = make_problem(n, h, bc, layout, 0, 0, &P);
+  if (rc) return rc;
+  if (dir < 0) {
+    const long V = user_dims(P).size();
+    std::vector<cd> f(V);
+    for (long i = 0; i < V; ++i) f[i] = in[i];
+    const std::vector<cd> F = forward3(P, f, MODE_FAST);
+    std::memcpy(out, F.data(), F.size() * sizeof(cd));
+    return 0;
+  }
+  const long S = (long)P.ax[0].nspec * P.ax[1].nspec * P.ax[2].nspec;
+  std::vector<cd> F(S);
+  std::memcpy(F.data(), in, S * sizeof(cd));
+  const std::vector<cd> u = backward3(P, F, MODE_FAST);
+  for (size_t i = 0; i < u.size(); ++i) out[i] = u[i].real();
+  return 0;
+}
+
 // Green's spectrum on the (unfolded) spectral grid, complex interleaved, [z][y][x].
 int oracle_green_spectrum(const int* n, const double* h, const int* bc, int layout, int green,
                           int mode, double* out) {
@@ -958,6 +984,15 @@ int oracle_num_threads(void) {
   return omp_get_max_threads();
 #else
   return 1;
+#endif
+}
+
+// Threads used by later calls (the CPU-baseline timing on one core and on all cores).
+void oracle_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
 #endif
 }
 

@@ -245,9 +245,15 @@ struct fm_plan_s {
   size_t elem;      // sizeof(real)
   size_t bytesA, bytesB;  // per component
   size_t ws_bytes;
-  fm::PassDesc pass[5];
+  // the five passes of a solve, then the last axis's plain forward (B -> spectrum) and
+  // backward (spectrum -> B) transforms of fm_fft_forward / fm_fft_backward
+  static constexpr int kPasses = 7;
+  fm::PassDesc pass[kPasses];
+  int ext_spec[3];
+  int64_t Vspec;
+  bool cplx_spec;
   void* G = nullptr;
-  fm::PassDesc* dpass = nullptr;  // the five descriptors in device memory
+  fm::PassDesc* dpass = nullptr;  // the descriptors in device memory
   int GF[3];
   std::map<int, void*> tw;
   std::map<int, void*> stw;
@@ -481,7 +487,7 @@ void release_generation(fm_plan_s* p) {
 template <typename T>
 int make_tables_and_green(fm_plan_s* p, hipStream_t st, bool deferred) {
   // twiddle tables for every FFT length of the passes
-  for (int i = 0; i < 5; ++i) {
+  for (int i = 0; i < fm_plan_s::kPasses; ++i) {
     const int M = p->pass[i].M;
     if (p->tw.count(M)) continue;
     void* ptr = nullptr;
@@ -490,9 +496,9 @@ int make_tables_and_green(fm_plan_s* p, hipStream_t st, bool deferred) {
     p->table_bytes += sizeof(T) * 2 * 4 * (size_t)M;
     FM_HIP(fm::launch_twiddles<T>(ptr, M, st));
   }
-  for (int i = 0; i < 5; ++i) p->pass[i].tw = p->tw[p->pass[i].M];
+  for (int i = 0; i < fm_plan_s::kPasses; ++i) p->pass[i].tw = p->tw[p->pass[i].M];
   // per-stage tables of the lengths with compile-time kernels
-  for (int i = 0; i < 5; ++i) {
+  for (int i = 0; i < fm_plan_s::kPasses; ++i) {
     const int M = p->pass[i].M;
     if (!compile_time_kernel(p->pass[i], p->elem)) continue;
     if (tile_in_span_bytes(p->pass[i], p->elem) >= (int64_t(1) << 32)) continue;
@@ -615,13 +621,13 @@ int make_tables_and_green(fm_plan_s* p, hipStream_t st, bool deferred) {
       FM_HIP(fm::launch_green_final<T>(p->G, S, F, Fs, off, scale, st));
     }
   }
-  // the five pass descriptors, now complete, go to device memory
-  for (int i = 0; i < 5; ++i) p->pass[i].g.G = p->G;
+  // the pass descriptors, now complete, go to device memory
+  for (int i = 0; i < fm_plan_s::kPasses; ++i) p->pass[i].g.G = p->G;
   if (rc == FM_OK) {
-    if (hipMalloc(&p->dpass, sizeof(fm::PassDesc) * 5) != hipSuccess) rc = FM_E_NOMEM;
-    else p->table_bytes += sizeof(fm::PassDesc) * 5;
-    if (rc == FM_OK)
-      FM_HIP(hipMemcpyAsync(p->dpass, p->pass, sizeof(fm::PassDesc) * 5, hipMemcpyHostToDevice, st));
+    const size_t nb = sizeof(fm::PassDesc) * fm_plan_s::kPasses;
+    if (hipMalloc(&p->dpass, nb) != hipSuccess) rc = FM_E_NOMEM;
+    else p->table_bytes += nb;
+    if (rc == FM_OK) FM_HIP(hipMemcpyAsync(p->dpass, p->pass, nb, hipMemcpyHostToDevice, st));
   }
   for (int i = 0; i < 3; ++i) p->GF[i] = F[i];
   if (deferred && rc == FM_OK) {
@@ -980,8 +986,39 @@ int build_plan(fm_plan_s* p) {
     p->pass[3].out_s_comp = compA;
     p->pass[4].in_s_comp = compA;
   }
-  const int line_axis[5] = {a0, a1, a2, a1, a0};
-  for (int i = 0; i < 5; ++i) {
+  // plain transforms along the last axis: B (L2, a2 extent wext) <-> spectrum buffer
+  // (L2 order, a2 extent nspec), one per component
+  {
+    const AxisPlan& A = p->ax[a2];
+    for (int a = 0; a < 3; ++a) p->ext_spec[a] = p->ext2[a];
+    p->ext_spec[a2] = A.nspec;
+    int64_t ss[3];
+    layout_strides(p->L2, p->ext_spec, ss, &p->Vspec);
+    p->cplx_spec = p->cplx2 || A.dft;
+    fm::PassDesc& f = p->pass[5];
+    f = fm::PassDesc{};
+    set_geometry(&f, a2, a1, a0, s2, p->V2, ss, p->Vspec, p->ext2);
+    set_transform(&f, A, true, false);
+    f.in_cplx = p->cplx2;
+    f.out_cplx = p->cplx_spec;
+    f.in_n = wext[a2];
+    f.out_n = A.nspec;
+    fm::PassDesc& g = p->pass[6];
+    g = fm::PassDesc{};
+    set_geometry(&g, a2, a1, a0, ss, p->Vspec, s2, p->V2, p->ext2);
+    set_transform(&g, A, false, false);
+    g.in_cplx = p->cplx_spec;
+    g.out_cplx = p->cplx2;
+    g.in_n = A.nspec;
+    g.out_n = wext[a2];
+    const int64_t compB = (int64_t)(p->bytesB / (p->elem * (p->cplx2 ? 2 : 1)));
+    f.in_s_comp = compB;
+    f.out_s_comp = p->Vspec;
+    g.in_s_comp = p->Vspec;
+    g.out_s_comp = compB;
+  }
+  const int line_axis[fm_plan_s::kPasses] = {a0, a1, a2, a1, a0, a2, a2};
+  for (int i = 0; i < fm_plan_s::kPasses; ++i) {
     fm::PassDesc& d = p->pass[i];
     const int rc = radix_plan(p->ax[line_axis[i]].M, &d);
     if (rc) return rc;
@@ -1011,10 +1048,10 @@ int build_plan(fm_plan_s* p) {
       }
     }
   }
-  for (int i = 0; i < 5; ++i) p->pass[i].kind = pass_kind(p->pass[i]);
-  const int64_t sizes_in[5] = {p->Vu, p->V1, p->V2, p->V2, p->V1};
-  const int64_t sizes_out[5] = {p->V1, p->V2, p->V2, p->V1, p->Vu};
-  for (int i = 0; i < 5; ++i)
+  for (int i = 0; i < fm_plan_s::kPasses; ++i) p->pass[i].kind = pass_kind(p->pass[i]);
+  const int64_t sizes_in[fm_plan_s::kPasses] = {p->Vu, p->V1, p->V2, p->V2, p->V1, p->V2, p->Vspec};
+  const int64_t sizes_out[fm_plan_s::kPasses] = {p->V1, p->V2, p->V2, p->V1, p->Vu, p->Vspec, p->V2};
+  for (int i = 0; i < fm_plan_s::kPasses; ++i)
     if (!pass_in_bounds(p->pass[i], sizes_in[i], sizes_out[i], p->elem)) return FM_E_SIZE;
   return FM_OK;
 }
@@ -1043,20 +1080,30 @@ bool sync_debug() {
   return v;
 }
 
+// Launch descriptor i of the plan on buffers in -> out.
+int launch_one(fm_plan_s* p, int i, const void* in, void* out, hipStream_t st) {
+  const fm::PassDesc& d = p->pass[i];
+  if (sync_debug()) {
+    std::fprintf(stderr, "fluxmi: pass %d kind %d M %d prec %s tiles %d B %d lds %d\n", i + 1, d.kind,
+                 d.M, p->prec == FM_F64 ? "f64" : "f32", d.tiles, d.B, d.lds_bytes);
+    std::fflush(stderr);
+  }
+  if (d.wave && !d.wtw) return FM_E_ARG;
+  hipError_t e = (p->prec == FM_F64) ? fm::launch_pass<double>(d, p->dpass + i, in, out, st)
+                                     : fm::launch_pass<float>(d, p->dpass + i, in, out, st);
+  if (e == hipSuccess && sync_debug()) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    g_last_hip = (int)e;
+    return FM_E_HIP;
+  }
+  return FM_OK;
+}
+
 int launch_all(fm_plan_s* p, const void* const ins[5], void* const outs[5], hipStream_t st,
                int first = 0, int last = 4) {
   for (int i = first; i <= last; ++i) {
-    const fm::PassDesc& d = p->pass[i];
-    if (sync_debug()) {
-      std::fprintf(stderr, "fluxmi: pass %d kind %d M %d prec %s tiles %d B %d lds %d\n", i + 1,
-                   d.kind, d.M, p->prec == FM_F64 ? "f64" : "f32", d.tiles, d.B, d.lds_bytes);
-      std::fflush(stderr);
-    }
-    hipError_t e = (p->prec == FM_F64)
-                       ? fm::launch_pass<double>(d, p->dpass + i, ins[i], outs[i], st)
-                       : fm::launch_pass<float>(d, p->dpass + i, ins[i], outs[i], st);
-    if (e == hipSuccess && sync_debug()) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) { g_last_hip = (int)e; return FM_E_HIP; }
+    const int rc = launch_one(p, i, ins[i], outs[i], st);
+    if (rc) return rc;
   }
   return FM_OK;
 }
@@ -1426,6 +1473,43 @@ int fm_solve_passes(fm_plan p, const void* rhs_dev, void* out_dev, void* workspa
   void* outs[5];
   bind_buffers(p, rhs_dev, out_dev, ws, ins, outs);
   return launch_all(p, ins, outs, st, first_pass, last_pass);
+}
+
+int fm_plan_spectrum_layout(fm_plan p, int dims[3], int axes[3], int* is_complex, size_t* bytes) {
+  if (!p || !dims || !axes || !is_complex || !bytes) return FM_E_NULL;
+  for (int i = 0; i < 3; ++i) {
+    axes[i] = p->L2[i];
+    dims[i] = p->ext_spec[p->L2[i]];
+  }
+  *is_complex = p->cplx_spec ? 1 : 0;
+  *bytes = (size_t)p->ncomp * (size_t)p->Vspec * p->elem * (p->cplx_spec ? 2 : 1);
+  return FM_OK;
+}
+
+int fm_fft_forward(fm_plan p, const void* in_dev, void* spec_dev, void* workspace_dev, void* hip_stream) {
+  if (!p || !in_dev || !spec_dev) return FM_E_NULL;
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  char* ws = reinterpret_cast<char*>(workspace_dev);
+  if (!ws && !(ws = own_workspace(p))) return FM_E_NOMEM;
+  char* A = ws;
+  char* B = ws + p->ncomp * p->bytesA;
+  int rc = launch_one(p, 0, in_dev, A, st);
+  if (rc == FM_OK) rc = launch_one(p, 1, A, B, st);
+  if (rc == FM_OK) rc = launch_one(p, 5, B, spec_dev, st);
+  return rc;
+}
+
+int fm_fft_backward(fm_plan p, const void* spec_dev, void* out_dev, void* workspace_dev, void* hip_stream) {
+  if (!p || !spec_dev || !out_dev) return FM_E_NULL;
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  char* ws = reinterpret_cast<char*>(workspace_dev);
+  if (!ws && !(ws = own_workspace(p))) return FM_E_NOMEM;
+  char* A = ws;
+  char* B = ws + p->ncomp * p->bytesA;
+  int rc = launch_one(p, 6, spec_dev, B, st);
+  if (rc == FM_OK) rc = launch_one(p, 3, B, A, st);
+  if (rc == FM_OK) rc = launch_one(p, 4, A, out_dev, st);
+  return rc;
 }
 
 int fm_batched_workspace_bytes(int count, const fm_plan* plans, size_t* bytes) {

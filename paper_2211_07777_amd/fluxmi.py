@@ -27,6 +27,7 @@ EXPORTED = [
     "fm_plan_tune", "fm_plan_tiling", "fm_plan_device_bytes",
     "fm_server_create", "fm_server_submit", "fm_server_progress", "fm_server_wait_all",
     "fm_server_get_stats", "fm_server_destroy", "fm_solve_static", "fm_plan_set_tiling",
+    "fm_plan_spectrum_layout", "fm_fft_forward", "fm_fft_backward",
 ]
 STATIC_WORKSPACE_BYTES = 128 << 20  # FM_STATIC_WORKSPACE_BYTES
 
@@ -83,6 +84,9 @@ def library():
     L.fm_solve.argtypes = [vp, vp, vp, vp, vp]
     L.fm_solve_passes.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_int, vp]
     L.fm_solve_static.argtypes = [vp, vp, vp, vp]
+    L.fm_plan_spectrum_layout.argtypes = [vp, ip, ip, ip, ctypes.POINTER(ctypes.c_size_t)]
+    L.fm_fft_forward.argtypes = [vp, vp, vp, vp, vp]
+    L.fm_fft_backward.argtypes = [vp, vp, vp, vp, vp]
     L.fm_solve_batched.argtypes = [ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                    ctypes.POINTER(vp), vp, ctypes.c_size_t, vp]
     L.fm_batched_workspace_bytes.argtypes = [ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_size_t)]
@@ -205,6 +209,51 @@ class Plan:
             ws = ctypes.c_void_p(workspace.data_ptr())
         _check(library().fm_solve(self._h, ctypes.c_void_p(rhs.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                   ws, _stream_ptr(stream)), "fm_solve")
+        return out
+
+    def spectrum_layout(self):
+        """(dims slow -> fast, physical axis of each, complex?, bytes) of the spectrum of
+        fft_forward (fm_plan_spectrum_layout)."""
+        d, a, c, b = (ctypes.c_int * 3)(), (ctypes.c_int * 3)(), ctypes.c_int(), ctypes.c_size_t()
+        _check(library().fm_plan_spectrum_layout(self._h, d, a, ctypes.byref(c), ctypes.byref(b)),
+               "fm_plan_spectrum_layout")
+        return list(d), list(a), bool(c.value), int(b.value)
+
+    def spectrum_empty(self):
+        """A torch tensor shaped for the spectrum: (ncomp,) + dims (+ complex dtype)."""
+        import torch
+        dims, _, cplx, _ = self.spectrum_layout()
+        shape = ((self.ncomp,) if self.ncomp > 1 else ()) + tuple(dims)
+        if cplx:
+            dt = torch.complex128 if self.prec == F64 else torch.complex64
+        else:
+            dt = self.dtype
+        return torch.empty(shape, dtype=dt, device="cuda")
+
+    def _check_spec(self, spec):
+        _, _, _, nbytes = self.spectrum_layout()
+        if not spec.is_cuda or not spec.is_contiguous() or spec.numel() * spec.element_size() != nbytes:
+            raise ValueError("spec: need a contiguous GPU tensor of fm_plan_spectrum_layout's size")
+
+    def fft_forward(self, x, spec=None, workspace=None, stream=None):
+        """Forward transforms of every axis, no spectral multiplication (fm_fft_forward)."""
+        self._check_tensor(x, "in")
+        spec = self.spectrum_empty() if spec is None else spec
+        self._check_spec(spec)
+        ws = ctypes.c_void_p(0 if workspace is None else workspace.data_ptr())
+        _check(library().fm_fft_forward(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(spec.data_ptr()),
+                                        ws, _stream_ptr(stream)), "fm_fft_forward")
+        return spec
+
+    def fft_backward(self, spec, out=None, workspace=None, stream=None):
+        """Backward transforms with the crop and output conventions (fm_fft_backward)."""
+        import torch
+        self._check_spec(spec)
+        out = torch.empty(self.shape, dtype=self.dtype, device="cuda") if out is None else out
+        self._check_tensor(out, "out")
+        ws = ctypes.c_void_p(0 if workspace is None else workspace.data_ptr())
+        _check(library().fm_fft_backward(self._h, ctypes.c_void_p(spec.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                         ws, _stream_ptr(stream)), "fm_fft_backward")
         return out
 
     def solve_static(self, rhs, out, stream=None):
