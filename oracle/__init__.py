@@ -11,7 +11,8 @@ spectrum (Eq. of Sec. II) or by the Green's spectrum times the spectral curl (Se
 
 Boundary codes: 0 even, 1 odd, 2 periodic, 3 unbounded.  Layout: 0 cell, 1 node.
 Green: 0 CHAT2 as printed in Sec. IV (sphere-mean self-term times the cell volume),
-1 the sphere-mean self-term itself.  Kind: 0 Poisson, 1 Biot-Savart (spectral curl).
+1 the sphere-mean self-term itself.  Kind: 0 Poisson, 1 Biot-Savart (spectral curl),
+2 / 3 / 4 Biot-Savart with the finite-difference curl of order 2 / 4 / 6.
 """
 from __future__ import annotations
 
@@ -133,7 +134,8 @@ def user_shape(n, layout):
 
 
 def solve(rhs, n, h, bc, layout, green=0, kind=0, mode=FAST):
-    """Solve lap(u) = f (kind 0) or lap(u) = curl(f) (kind 1).
+    """Solve lap(u) = f (kind 0) or lap(u) = curl(f) (kind 1: spectral derivative; 2, 3, 4:
+    finite-difference derivative of order 2, 4, 6).
 
     rhs: array [nz, ny, nx] (Poisson) or [3, nz, ny, nx] (Biot-Savart), FP64.
     n: intervals (node) or cells (cell) per axis (x, y, z); h: spacing per axis;
@@ -141,11 +143,11 @@ def solve(rhs, n, h, bc, layout, green=0, kind=0, mode=FAST):
     """
     n, h, bc = _prep(n, h, bc)
     shp = user_shape(n, layout)
-    ncomp = 3 if kind == 1 else 1
+    ncomp = 3 if kind >= 1 else 1
     rhs = np.ascontiguousarray(rhs, dtype=np.float64).reshape((ncomp,) + shp)
     out = np.empty_like(rhs)
     _check(lib().oracle_solve(_ip(n), _dp(h), _ip(bc), layout, green, kind, mode, _dp(rhs), _dp(out)))
-    return out if kind == 1 else out[0]
+    return out if kind >= 1 else out[0]
 
 
 def direct_points(rhs, n, h, bc, layout, points, green=0):

@@ -501,7 +501,8 @@ struct Problem {
   Axis ax[3];
   int du = 0;
   Green g;
-  int kind = 0;  // 0 Poisson, 1 Biot-Savart with spectral curl
+  int kind = 0;  // 0 Poisson, 1 Biot-Savart with spectral curl, 2 / 3 / 4 Biot-Savart with
+                 // the finite-difference derivative of order 2 / 4 / 6 (Sec. V)
 };
 
 int make_problem(const int* n, const double* h, const int* bc, int layout, int green, int kind,
@@ -511,9 +512,9 @@ int make_problem(const int* n, const double* h, const int* bc, int layout, int g
     if (rc) return rc;
   }
   if (green != 0 && green != 1) return -3;
-  if (kind != 0 && kind != 1) return -3;
+  if (kind < 0 || kind > 4) return -3;
   P->kind = kind;
-  if (kind == 1)
+  if (kind >= 1)
     for (int a = 0; a < 3; ++a)
       if (!P->ax[a].dft) return -3;  // spectral curl on periodic / fully unbounded axes only
   P->du = 0;
@@ -636,7 +637,7 @@ int solve_spectral(const Problem& P, const double* rhs, double* out, int mode) {
   const Dims du = user_dims(P);
   const long V = du.size();
   const std::vector<cd> G = green_spectrum(P, mode);
-  const int ncomp = (P.kind == 1) ? 3 : 1;
+  const int ncomp = (P.kind >= 1) ? 3 : 1;
   std::vector<std::vector<cd>> fh(ncomp);
   for (int c = 0; c < ncomp; ++c) {
     std::vector<cd> f(V);
@@ -647,16 +648,25 @@ int solve_spectral(const Problem& P, const double* rhs, double* out, int mode) {
   if (P.kind == 0) {
     for (long i = 0; i < nx * ny * nz; ++i) fh[0][i] *= G[i];
   } else {
-    // u_hat = G_hat * (i w x f_hat)   (Sec. V)
+    // u_hat = G_hat * (i w x f_hat)   (Sec. V); the finite-difference forms replace the
+    // wavenumber w of each axis by its central-difference symbol
     const cd I(0.0, 1.0);
+    auto deriv = [&](const Axis& A, int s) {
+      const double w = omega(A, s, true);
+      if (P.kind == 1) return w;
+      const double wh = omega(A, s, false) * A.h;  // the symbols vanish at the Nyquist mode
+      if (P.kind == 2) return std::sin(wh) / A.h;
+      if (P.kind == 3) return (4.0 / 3.0 * std::sin(wh) - 1.0 / 6.0 * std::sin(2.0 * wh)) / A.h;
+      return (1.5 * std::sin(wh) - 0.3 * std::sin(2.0 * wh) + std::sin(3.0 * wh) / 30.0) / A.h;
+    };
 #pragma omp parallel for collapse(2) schedule(static)
     for (long z = 0; z < nz; ++z)
       for (long y = 0; y < ny; ++y)
         for (long x = 0; x < nx; ++x) {
           const long i = x + nx * (y + ny * z);
-          const double wx = omega(P.ax[0], (int)x, true);
-          const double wy = omega(P.ax[1], (int)y, true);
-          const double wz = omega(P.ax[2], (int)z, true);
+          const double wx = deriv(P.ax[0], (int)x);
+          const double wy = deriv(P.ax[1], (int)y);
+          const double wz = deriv(P.ax[2], (int)z);
           const cd fx = fh[0][i], fy = fh[1][i], fz = fh[2][i];
           fh[0][i] = G[i] * I * (wy * fz - wz * fy);
           fh[1][i] = G[i] * I * (wz * fx - wx * fz);
@@ -913,7 +923,9 @@ double oracle_green_value(int du, int variant, double cellvol, double rho, doubl
 // Solve.  n[3] = cells / intervals per axis (x, y, z); h[3]; bc[6] = (x-left, x-right,
 // y-left, y-right, z-left, z-right) with 0 even, 1 odd, 2 periodic, 3 unbounded;
 // layout 0 cell / 1 node; green 0 (CHAT2 as printed) / 1 (sphere-mean self-term);
-// kind 0 Poisson / 1 Biot-Savart (3 components); mode 0 fast / 1 naive / 2 direct.
+// kind 0 Poisson / 1 Biot-Savart with the spectral curl / 2, 3, 4 Biot-Savart with the
+// finite-difference derivative of order 2, 4, 6 (3 components); mode 0 fast / 1 naive /
+// 2 direct (Poisson only).
 // rhs, out: [ncomp][nz][ny][nx] doubles with the user's point counts.
 int oracle_solve(const int* n, const double* h, const int* bc, int layout, int green, int kind,
                  int mode, const double* rhs, double* out) {
