@@ -55,8 +55,17 @@ typedef enum { FM_F64 = 0, FM_F32 = 1 } fm_prec;
 
 /* Poisson: lap(u) = f.  Biot-Savart: lap(u) = curl(f) with the curl taken in
  * spectral space as i*omega x f_hat (Sec. V); needs periodic or fully unbounded
- * conditions on every axis and ncomp = 3. */
-typedef enum { FM_POISSON = 0, FM_BIOT_SAVART = 1 } fm_kind;
+ * conditions on every axis and ncomp = 3.  The _FD kinds replace the derivative i*omega
+ * by the symbol of the central difference of order 2, 4 or 6 (Sec. V):
+ * (i/h) sin(w h), (i/h) (4/3 sin(w h) - 1/6 sin(2 w h)),
+ * (i/h) (3/2 sin(w h) - 3/10 sin(2 w h) + 1/30 sin(3 w h)), h the spacing of the axis. */
+typedef enum {
+  FM_POISSON = 0,
+  FM_BIOT_SAVART = 1,
+  FM_BIOT_SAVART_FD2 = 2,
+  FM_BIOT_SAVART_FD4 = 3,
+  FM_BIOT_SAVART_FD6 = 4
+} fm_kind;
 
 /* Status codes. */
 #define FM_OK 0

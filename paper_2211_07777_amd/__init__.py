@@ -4,7 +4,8 @@ The compute path is the HIP library ``libfluxmi.so`` (C ABI, ``include/fluxmi.h`
 this package only marshals arguments (torch tensors for device memory and streams).
 """
 from .fluxmi import (  # noqa: F401
-    CELL, NODE, EVEN, ODD, PER, UNB, F64, F32, POISSON, BIOT_SAVART, CHAT2, CHAT2_VOL,
+    CELL, NODE, EVEN, ODD, PER, UNB, F64, F32, POISSON, BIOT_SAVART, BIOT_SAVART_FD2, BIOT_SAVART_FD4,
+    BIOT_SAVART_FD6, CHAT2, CHAT2_VOL,
     FluxmiError, Plan, Batch, Server, plan_inspect, solve_batched, batched_workspace_bytes, library,
     error_string,
 )

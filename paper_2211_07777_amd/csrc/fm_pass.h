@@ -100,6 +100,10 @@ struct GreenRef {
   int32_t axis_line, axis_b, axis_c;  // physical axis (0 x, 1 y, 2 z) of each direction
   double dw_line, dw_b, dw_c;         // 2 pi / period
   int32_t M_line, M_b, M_c;           // DFT lengths for the signed-mode map
+  // derivative of the curl: 0 spectral (i w), 2 / 4 / 6 the central-difference symbol of
+  // that order, i/h sum_j c_j sin(j w h) with w h = 2 pi k / M (Sec. V)
+  int32_t deriv;
+  double ih_line, ih_b, ih_c;         // 1 / h per direction
 };
 
 // Output conventions applied by the last pass along its two batch axes (Sec. II-A,

@@ -801,7 +801,7 @@ int build_plan(fm_plan_s* p) {
     const int rc = plan_axis(p->n[a], p->h[a], node, p->bc[a][0], p->bc[a][1], &p->ax[a]);
     if (rc) return rc;
   }
-  if (p->kind == FM_BIOT_SAVART) {
+  if (p->kind != FM_POISSON) {
     if (p->ncomp != 3) return FM_E_KIND;
     for (int a = 0; a < 3; ++a)
       if (!p->ax[a].dft) return FM_E_KIND;
@@ -877,7 +877,7 @@ int build_plan(fm_plan_s* p) {
   p->ws_bytes = (size_t)p->ncomp * (p->bytesA + p->bytesB);
 
   const int o1 = 3 - a0 - p->tb1;  // the other axis of passes 1 / 5
-  const bool curl = p->kind == FM_BIOT_SAVART;
+  const bool curl = p->kind != FM_POISSON;
   // pass 1: user -> L1 along a0
   {
     fm::PassDesc& d = p->pass[0];
@@ -940,6 +940,11 @@ int build_plan(fm_plan_s* p) {
     g.M_line = A.M;
     g.M_b = p->ax[a1].M;
     g.M_c = p->ax[a0].M;
+    g.deriv = p->kind == FM_BIOT_SAVART_FD2 ? 2 : p->kind == FM_BIOT_SAVART_FD4 ? 4
+            : p->kind == FM_BIOT_SAVART_FD6 ? 6 : 0;
+    g.ih_line = 1.0 / A.h;
+    g.ih_b = 1.0 / p->ax[a1].h;
+    g.ih_c = 1.0 / p->ax[a0].h;
   }
   // pass 4: L2 -> L1 along a1 (inverse of pass 2)
   {
@@ -1302,7 +1307,7 @@ int check_enums(int layout, int green, int prec, int kind, int ncomp) {
   if (layout != FM_CELL && layout != FM_NODE) return FM_E_KIND;
   if (green != FM_GREEN_CHAT2 && green != FM_GREEN_CHAT2_VOL) return FM_E_KIND;
   if (prec != FM_F64 && prec != FM_F32) return FM_E_KIND;
-  if (kind != FM_POISSON && kind != FM_BIOT_SAVART) return FM_E_KIND;
+  if (kind < FM_POISSON || kind > FM_BIOT_SAVART_FD6) return FM_E_KIND;
   if (ncomp < 1 || ncomp > 64) return FM_E_KIND;
   return FM_OK;
 }
@@ -1576,7 +1581,7 @@ int launch_mode(const fm::PassDesc& d, size_t elem) {
 // compile-time-length kernels address a tile with 32-bit offsets).
 bool retile(const fm_plan_s* p, int i, int bmax, int mode, fm::PassDesc* out) {
   fm::PassDesc d = p->pass[i];
-  const bool fused_curl = (i == 2) && p->kind == FM_BIOT_SAVART;
+  const bool fused_curl = (i == 2) && p->kind != FM_POISSON;
   const int64_t sizes_in[5] = {p->Vu, p->V1, p->V2, p->V2, p->V1};
   const int64_t sizes_out[5] = {p->V1, p->V2, p->V2, p->V1, p->Vu};
   d.wave = 0;

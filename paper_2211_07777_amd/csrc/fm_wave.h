@@ -144,12 +144,13 @@ __device__ __forceinline__ void wave_tile(const PassDesc& d, const void* in, voi
     wave_stages<T, M, 0, -1>(v[q], j, buf, tw);
   }
   if constexpr (KIND == K_F_CURL) {
-    const T wc = signed_wave<T>(ti.c, d.g.M_c, T(d.g.dw_c));
-    const T wb = signed_wave<T>(b, d.g.M_b, T(d.g.dw_b));
+    const T wc = curl_wave<T>(ti.c, d.g.M_c, T(d.g.dw_c), T(d.g.ih_c), d.g.deriv);
+    const T wb = curl_wave<T>(b, d.g.M_b, T(d.g.dw_b), T(d.g.ih_b), d.g.deriv);
+    const T ihl = T(d.g.ih_line);
     const T dwl = T(d.g.dw_line);
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-      const T wl = signed_wave<T>(j + P * m, d.g.M_line, dwl);
+      const T wl = curl_wave<T>(j + P * m, d.g.M_line, dwl, ihl, d.g.deriv);
       const T wx = d.g.axis_line == 0 ? wl : (d.g.axis_b == 0 ? wb : wc);
       const T wy = d.g.axis_line == 1 ? wl : (d.g.axis_b == 1 ? wb : wc);
       const T wz = d.g.axis_line == 2 ? wl : (d.g.axis_b == 2 ? wb : wc);

@@ -18,7 +18,7 @@ EVEN, ODD, PER, UNB = 0, 1, 2, 3
 CELL, NODE = 0, 1
 CHAT2, CHAT2_VOL = 0, 1
 F64, F32 = 0, 1
-POISSON, BIOT_SAVART = 0, 1
+POISSON, BIOT_SAVART, BIOT_SAVART_FD2, BIOT_SAVART_FD4, BIOT_SAVART_FD6 = 0, 1, 2, 3, 4
 CLASS_NAMES = ["P", "EE", "OO", "EO", "OE", "UU", "EU", "OU", "UE", "UO"]
 EXPORTED = [
     "fm_plan_create", "fm_plan_destroy", "fm_plan_workspace_bytes", "fm_plan_shape",
@@ -164,7 +164,7 @@ class Plan:
 
     def __init__(self, n, h, bc, layout, green=CHAT2, prec=F64, kind=POISSON, ncomp=None, stream=None):
         if ncomp is None:
-            ncomp = 3 if kind == BIOT_SAVART else 1
+            ncomp = 3 if kind != POISSON else 1
         self.n, self.h, self.bc = tuple(int(v) for v in n), tuple(float(v) for v in h), [list(p) for p in bc]
         self.layout, self.green, self.prec, self.kind, self.ncomp = layout, green, prec, kind, ncomp
         n3, h3, b6 = _args(n, h, bc)

@@ -17,8 +17,8 @@ PAIRS = [(2, 2), (0, 0), (1, 1), (0, 1), (1, 0), (3, 3), (0, 3), (1, 3), (3, 0),
 
 
 def _case(n, h, bc, layout, prec, seed, green=0, kind=0):
-    ncomp = 3 if kind == 1 else 1
-    shape = ((3,) if kind == 1 else ()) + O.user_shape(n, layout)
+    ncomp = 3 if kind != 0 else 1
+    shape = ((3,) if kind != 0 else ()) + O.user_shape(n, layout)
     f = W.random_field(shape, seed)
     ref = oracle_solve(f, n, h, bc, layout, green, kind)
     plan = F.Plan(n, h, bc, layout, green, prec, kind, ncomp)
@@ -227,3 +227,35 @@ def test_per_wavefront_fused_kernel(M, prec, tol):
             err = rel_linf(u, ref)
             assert err < tol, (M, n, bc, layout, kind, waves, err)
         plan.close()
+
+
+@pytest.mark.parametrize("prec,tol", [(F.F64, TOL64), (F.F32, TOL32)])
+@pytest.mark.parametrize("kind", [F.BIOT_SAVART_FD2, F.BIOT_SAVART_FD4, F.BIOT_SAVART_FD6])
+def test_biot_savart_finite_difference(kind, prec, tol):
+    """The curl with the central-difference symbols of order 2, 4, 6 (Sec. V), periodic
+    and unbounded axes, both layouts; a power-of-two last axis runs the per-wavefront
+    kernel (FP32) and, re-tiled, the LDS-tile kernel."""
+    for layout in (F.CELL, F.NODE):
+        for bc in ([[3, 3]] * 3, [[2, 2], [3, 3], [3, 3]], [[3, 3], [2, 2], [2, 2]], [[2, 2]] * 3):
+            err = _case([12, 10, 14], [0.1, 0.12, 0.09], bc, layout, prec, 5, kind=kind)
+            assert err < tol, (bc, layout, prec, kind, err)
+    n, h, bc = [6, 5, 16], [0.1, 0.12, 1 / 16], [[3, 3], [2, 2], [3, 3]]
+    f = W.random_field((3,) + O.user_shape(n, F.CELL), 8)
+    ref = oracle_solve(f, n, h, bc, F.CELL, 0, kind)
+    plan = F.Plan(n, h, bc, F.CELL, F.CHAT2, prec, kind, 3)
+    t = plan.tiling()
+    modes = [t["persistent"][2]]
+    err = rel_linf(gpu_solve(plan, f), ref)
+    assert err < tol, (t, err)
+    for mode in (0, 2):
+        b, q = list(t["lines_per_tile"]), list(t["persistent"])
+        b[2], q[2] = 1, mode
+        try:
+            plan.set_tiling(b, q)
+        except F.FluxmiError:
+            continue
+        modes.append(mode)
+        err = rel_linf(gpu_solve(plan, f), ref)
+        assert err < tol, (mode, err)
+    plan.close()
+    assert (3 in modes) == (prec == F.F32) and len(modes) >= 2, modes
