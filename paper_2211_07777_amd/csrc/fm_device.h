@@ -669,19 +669,11 @@ __device__ __forceinline__ T signed_wave(int k, int M, T dw) {
   return dw * T(ks);
 }
 
-// Derivative factor of DFT mode k (length M) in the curl: the spectral wavenumber, or
-// the symbol of the central difference of order `deriv` (Sec. V), which vanishes at the
-// Nyquist mode by itself.
+// Derivative factor of DFT mode k in the curl, from the direction's table: the spectral
+// wavenumber (0 at the Nyquist mode) or the plan's central-difference symbol (Sec. V).
 template <typename T>
-__device__ __forceinline__ T curl_wave(int k, int M, T dw, T ih, int deriv) {
-  if (deriv == 0) return signed_wave<T>(k, M, dw);
-  const int ks = (2 * k > M) ? k - M : k;
-  auto s = [&](int j) {  // sin(j w h) = sin(pi 2 j ks / M)
-    return sinpi(T(2 * j * ks) / T(M));
-  };
-  if (deriv == 2) return ih * s(1);
-  if (deriv == 4) return ih * (T(4) / T(3) * s(1) - T(1) / T(6) * s(2));
-  return ih * (T(3) / T(2) * s(1) - T(3) / T(10) * s(2) + T(1) / T(30) * s(3));
+__device__ __forceinline__ T curl_wave(int k, const void* tab) {
+  return gptr<T>(tab)[k];
 }
 
 struct TileIdx {
@@ -955,8 +947,7 @@ __device__ void fused_compute(const PassDesc& d, void* out, const TileIdx& ti, c
     }
     fft_lines<T, MC, +1>(buf, ls, F, d, tb.stw, lds_g, min(d.out_n, M));
   } else {
-    const T wc = curl_wave<T>(c, d.g.M_c, T(d.g.dw_c), T(d.g.ih_c), d.g.deriv);
-    const T dwl = T(d.g.dw_line), dwb = T(d.g.dw_b);
+    const T wc = curl_wave<T>(c, d.g.dtab_c);
     struct Tri {
       cpx<T> x, y, z;
     };
@@ -965,8 +956,8 @@ __device__ void fused_compute(const PassDesc& d, void* out, const TileIdx& ti, c
         [&](int e) {
           const int l = e / M, k = e - l * M;
           const T g = gl[l * FL + fold_index(k, d.g.fold_line)];
-          const T wl = curl_wave<T>(k, d.g.M_line, dwl, T(d.g.ih_line), d.g.deriv);
-          const T wb = curl_wave<T>(b0 + l, d.g.M_b, dwb, T(d.g.ih_b), d.g.deriv);
+          const T wl = curl_wave<T>(k, d.g.dtab_line);
+          const T wb = curl_wave<T>(b0 + l, d.g.dtab_b);
           const T wx = d.g.axis_line == 0 ? wl : (d.g.axis_b == 0 ? wb : wc);
           const T wy = d.g.axis_line == 1 ? wl : (d.g.axis_b == 1 ? wb : wc);
           const T wz = d.g.axis_line == 2 ? wl : (d.g.axis_b == 2 ? wb : wc);

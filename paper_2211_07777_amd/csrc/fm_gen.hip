@@ -38,11 +38,11 @@ __global__ void stage_twiddle_kernel(cpx<T>* out, int M) {
 // Stage twiddles of the per-wavefront kernels: stage s >= 1 (radix R, Ns) holds
 // W_{Ns R}^{k r} at wave_tw_offset(M, s) + (r - 1) Ns + k.
 template <typename T>
-__global__ void wave_twiddle_kernel(cpx<T>* out, int M) {
+__global__ void wave_twiddle_kernel(cpx<T>* out, int M, int E) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  for (int s = 1; wave_radix(M, s) != 0; ++s) {
-    const int R = wave_radix(M, s), Ns = wave_ns(M, s);
-    const int off = wave_tw_offset(M, s);
+  for (int s = 1; wave_radix(M, s, E) != 0; ++s) {
+    const int R = wave_radix(M, s, E), Ns = wave_ns(M, s, E);
+    const int off = wave_tw_offset(M, s, E);
     if (e >= off && e < off + Ns * (R - 1)) {
       const int r = (e - off) / Ns + 1, k = (e - off) % Ns;
       const long long num = 2LL * k * r;  // angle 2 pi k r / (Ns R) = pi num / (Ns R)
@@ -235,11 +235,11 @@ hipError_t launch_stage_twiddles(void* out, int M, hipStream_t st) {
 }
 
 template <typename T>
-hipError_t launch_wave_twiddles(void* out, int M, hipStream_t st) {
-  const int n = wave_tw_size(M);
+hipError_t launch_wave_twiddles(void* out, int M, int E, hipStream_t st) {
+  const int n = wave_tw_size(M, E);
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(wave_twiddle_kernel<T>, dim3((n + 255) / 256), dim3(256), 0, st,
-                     reinterpret_cast<cpx<T>*>(out), M);
+                     reinterpret_cast<cpx<T>*>(out), M, E);
   return hipGetLastError();
 }
 
@@ -266,8 +266,8 @@ template hipError_t launch_pass_batched<float>(int, const PassDesc*, const int*,
 template hipError_t launch_pass_batched<double>(int, const PassDesc*, const int*, int, int, int, hipStream_t);
 template hipError_t launch_twiddles<float>(void*, int, hipStream_t);
 template hipError_t launch_twiddles<double>(void*, int, hipStream_t);
-template hipError_t launch_wave_twiddles<float>(void*, int, hipStream_t);
-template hipError_t launch_wave_twiddles<double>(void*, int, hipStream_t);
+template hipError_t launch_wave_twiddles<float>(void*, int, int, hipStream_t);
+template hipError_t launch_wave_twiddles<double>(void*, int, int, hipStream_t);
 template hipError_t launch_stage_twiddles<float>(void*, int, hipStream_t);
 template hipError_t launch_stage_twiddles<double>(void*, int, hipStream_t);
 template hipError_t launch_green_final<float>(void*, const double*, const int*, const int*, const int*, double, hipStream_t);

@@ -24,27 +24,36 @@ static hipError_t allow_full_lds() {
   return once;
 }
 
-// Fused complex passes in the per-wavefront kernel: d.B / wave_lines(M) wavefronts per
-// workgroup, one workgroup per tile.  FP64 three-component (curl) lines would hold 48
-// complex doubles per lane and are not built.
-template <int KIND>
-static hipError_t launch_wave(const PassDesc& d, const PassDesc* dev, const void* in, void* out,
-                              hipStream_t st) {
-  if constexpr (wave_length(FM_MC) &&
-                (KIND == K_F_C2C || (KIND == K_F_CURL && sizeof(FM_T) == 4))) {
-    const int threads = 64 * (d.B / wave_lines(FM_MC));
+// Fused complex passes in the per-wavefront kernel with E values per lane: d.B /
+// wave_lines(M, E) wavefronts per workgroup, one workgroup per tile.  Three-component
+// (curl) lines of 16 values per lane are built in FP32 only (in FP64 they would hold 48
+// complex doubles per lane).
+template <int KIND, int E>
+static hipError_t launch_wave_e(const PassDesc& d, const PassDesc* dev, const void* in, void* out,
+                                hipStream_t st) {
+  if constexpr (wave_length(FM_MC, E) &&
+                (KIND == K_F_C2C || (KIND == K_F_CURL && (sizeof(FM_T) == 4 || E == 8)))) {
+    const int threads = 64 * (d.B / wave_lines(FM_MC, E));
     if (threads < 64 || threads > kThreads) return hipErrorInvalidValue;
     if (d.lds_bytes > kSoftLds) {
-      const hipError_t e = allow_full_lds<&wave_pass_kernel<FM_T, FM_MC, KIND>>();
+      const hipError_t e = allow_full_lds<&wave_pass_kernel<FM_T, FM_MC, KIND, E>>();
       if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((wave_pass_kernel<FM_T, FM_MC, KIND>), dim3(d.tiles), dim3(threads), d.lds_bytes,
-                       st, dev, in, out);
+    hipLaunchKernelGGL((wave_pass_kernel<FM_T, FM_MC, KIND, E>), dim3(d.tiles), dim3(threads),
+                       d.lds_bytes, st, dev, in, out);
     return hipGetLastError();
   } else {
     (void)d; (void)dev; (void)in; (void)out; (void)st;
     return hipErrorInvalidValue;
   }
+}
+
+template <int KIND>
+static hipError_t launch_wave(const PassDesc& d, const PassDesc* dev, const void* in, void* out,
+                              hipStream_t st) {
+  if (d.wave == 16) return launch_wave_e<KIND, 16>(d, dev, in, out, st);
+  if (d.wave == 8) return launch_wave_e<KIND, 8>(d, dev, in, out, st);
+  return hipErrorInvalidValue;
 }
 
 template <int KIND>

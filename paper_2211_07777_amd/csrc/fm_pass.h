@@ -101,9 +101,13 @@ struct GreenRef {
   double dw_line, dw_b, dw_c;         // 2 pi / period
   int32_t M_line, M_b, M_c;           // DFT lengths for the signed-mode map
   // derivative of the curl: 0 spectral (i w), 2 / 4 / 6 the central-difference symbol of
-  // that order, i/h sum_j c_j sin(j w h) with w h = 2 pi k / M (Sec. V)
+  // that order, i/h sum_j c_j sin(j w h) with w h = 2 pi k / M (Sec. V); the kernels read
+  // the factor of every mode of the three directions from tables in the working precision
+  // (generated in FP64)
   int32_t deriv;
-  double ih_line, ih_b, ih_c;         // 1 / h per direction
+  const void* dtab_line;
+  const void* dtab_b;
+  const void* dtab_c;
 };
 
 // Output conventions applied by the last pass along its two batch axes (Sec. II-A,
@@ -139,39 +143,41 @@ constexpr int radix_at(int M, int s, int rmax) {
 // LDS banks; lines are fft_line_stride(M) slots apart.
 constexpr int fft_line_stride(int M) { return M + (M >> 4) + 1; }
 
-// Per-wavefront fused kernels (complex lines of a power-of-two length M, 32 <= M <= 1024):
-// each lane holds kWaveValues points of a line, so a line spans P = M / kWaveValues
-// lanes.  Radix schedule: kWaveValues first, then min(kWaveValues, rest) until the
-// product is M.  Stage s >= 1 reads its twiddles W_{Ns R}^{k r} (Ns = product of the
-// earlier radices, 1 <= r < R, k < Ns) from a table at wave_tw_offset(M, s) + (r-1) Ns + k.
+// Per-wavefront fused kernels (complex lines of a power-of-two length M): each lane holds
+// E points of a line (E = 16, or 8 for lines of at most 512 points), so a line spans
+// P = M / E <= 64 lanes.  Radix schedule: E first, then min(E, rest) until the product is
+// M.  Stage s >= 1 reads its twiddles W_{Ns R}^{k r} (Ns = product of the earlier radices,
+// 1 <= r < R, k < Ns) from a table at wave_tw_offset(M, s, E) + (r-1) Ns + k.
 constexpr int kWaveValues = 16;
-constexpr bool wave_length(int M) {
-  return M >= 2 * kWaveValues && M <= 64 * kWaveValues && (M & (M - 1)) == 0;
+constexpr bool wave_length(int M, int E = kWaveValues) {
+  return (E == 8 || E == 16) && M >= 2 * E && M <= 64 * E && (M & (M - 1)) == 0;
 }
-constexpr int wave_radix(int M, int s) {
-  int rest = M / kWaveValues;
-  if (s == 0) return kWaveValues;
-  for (int i = 1; i < s; ++i) rest /= (rest < kWaveValues ? rest : kWaveValues);
-  return rest <= 1 ? 0 : (rest < kWaveValues ? rest : kWaveValues);
+constexpr int wave_radix(int M, int s, int E = kWaveValues) {
+  int rest = M / E;
+  if (s == 0) return E;
+  for (int i = 1; i < s; ++i) rest /= (rest < E ? rest : E);
+  return rest <= 1 ? 0 : (rest < E ? rest : E);
 }
-constexpr int wave_ns(int M, int s) {
+constexpr int wave_ns(int M, int s, int E = kWaveValues) {
   int n = 1;
-  for (int i = 0; i < s; ++i) n *= wave_radix(M, i);
+  for (int i = 0; i < s; ++i) n *= wave_radix(M, i, E);
   return n;
 }
-constexpr int wave_tw_offset(int M, int s) {
+constexpr int wave_tw_offset(int M, int s, int E = kWaveValues) {
   int off = 0;
-  for (int i = 1; i < s; ++i) off += wave_ns(M, i) * (wave_radix(M, i) - 1);
+  for (int i = 1; i < s; ++i) off += wave_ns(M, i, E) * (wave_radix(M, i, E) - 1);
   return off;
 }
-constexpr int wave_stage_count(int M) {
+constexpr int wave_stage_count(int M, int E = kWaveValues) {
   int s = 0;
-  while (wave_radix(M, s) != 0) ++s;
+  while (wave_radix(M, s, E) != 0) ++s;
   return s;
 }
-constexpr int wave_tw_size(int M) { return wave_tw_offset(M, wave_stage_count(M)); }
+constexpr int wave_tw_size(int M, int E = kWaveValues) {
+  return wave_tw_offset(M, wave_stage_count(M, E), E);
+}
 // lines one wavefront holds (0 for lengths the per-wavefront kernels do not serve)
-constexpr int wave_lines(int M) { return wave_length(M) ? 64 / (M / kWaveValues) : 0; }
+constexpr int wave_lines(int M, int E = kWaveValues) { return wave_length(M, E) ? 64 / (M / E) : 0; }
 
 // Lengths with compile-time kernels (other lengths use the runtime-length kernel).
 constexpr int kFastLens[] = {32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 2048, 4096};
@@ -246,8 +252,10 @@ struct PassDesc {
                             // staged in LDS (persistent loop, or one tile per workgroup);
                             // 0 = one tile per workgroup reading them from global memory
   int32_t wave;             // fused complex pass in the per-wavefront kernel (fm_wave.h):
-                            // B = lines per workgroup, a multiple of wave_lines(M)
-  const void* wtw;          // its stage twiddle table (wave_tw_size(M) entries)
+                            // its values per lane E (16 or 8; 0: not that kernel); B =
+                            // lines per workgroup, a multiple of wave_lines(M, E)
+  const void* wtw;          // its stage twiddle tables: E = 16 (wave_tw_size(M, 16) entries)
+  const void* wtw8;         // and E = 8
 };
 
 // Sampling description of the Green's function for the spectrum generation (FP64).

@@ -27,7 +27,7 @@ hipError_t launch_pass_batched(int len_class, const PassDesc* ds, const int* pre
                                int total_tiles, int lds_bytes, hipStream_t st);
 template <typename T> hipError_t launch_twiddles(void* out, int M, hipStream_t st);
 template <typename T> hipError_t launch_stage_twiddles(void* out, int M, hipStream_t st);
-template <typename T> hipError_t launch_wave_twiddles(void* out, int M, hipStream_t st);
+template <typename T> hipError_t launch_wave_twiddles(void* out, int M, int E, hipStream_t st);
 bool is_fast_len(int M);
 
 hipError_t launch_green_sample(double* S, const GreenGen& g, hipStream_t st);
@@ -259,6 +259,7 @@ struct fm_plan_s {
   std::map<int, void*> stw;
   std::map<int, void*> tw64;
   std::map<int, void*> wtw;  // stage twiddles of the per-wavefront kernels
+  void* dtab = nullptr;      // central-difference symbols of the curl (line, b, c tables)
   void* ws_internal = nullptr;
   std::mutex ws_mu;  // guards the lazy allocation of ws_internal
   // Deferred creation (serving loop): the generation kernels may still run when the
@@ -389,28 +390,45 @@ int choose_tile(fm::PassDesc* d, size_t elem, int comps, bool fused_r2r, int nb,
   return FM_E_SIZE;
 }
 
-// The per-wavefront fused kernel (fm_wave.h): complex fused passes of a power-of-two
-// length whose lines are contiguous in memory (every fused complex pass: the last axis
-// is the fastest of its layout); three-component lines in FP32 only.
-bool wave_capable(const fm::PassDesc& d, size_t elem) {
-  if (!d.fused || d.gather != fm::G_CPLX || d.long_rt || !fm::wave_length(d.M)) return false;
-  if (d.g.curl && elem != 4) return false;
+// The per-wavefront fused kernel (fm_wave.h) with E values per lane: complex fused
+// passes of a power-of-two length whose lines are contiguous in memory (every fused
+// complex pass: the last axis is the fastest of its layout); three-component lines of 16
+// values per lane in FP32 only.
+bool wave_capable(const fm::PassDesc& d, size_t elem, int E) {
+  // the kernels are compiled with the compile-time-length classes (fm_inst.hip)
+  if (!d.fused || d.gather != fm::G_CPLX || d.long_rt || !fm::wave_length(d.M, E) || !fm::is_fast_len(d.M))
+    return false;
+  if (d.g.curl && elem != 4 && E == 16) return false;
   return d.in_s_line == 1 && d.out_s_line == 1;
+}
+
+bool wave_capable(const fm::PassDesc& d, size_t elem) {
+  return wave_capable(d, elem, 16) || wave_capable(d, elem, 8);
+}
+
+// Values per lane the planner gives a fused pass in the per-wavefront kernel: 8 for
+// three-component lines when their length allows it (three 8-value FP32 lines fit the
+// registers of three waves per SIMD, three 16-value lines need the 256 of two), else
+// 16.  FP64 three-component lines stay on the LDS-tile kernel unless the tuner picks
+// otherwise.
+int default_wave_values(const fm::PassDesc& d, size_t elem) {
+  if (d.g.curl && wave_capable(d, elem, 8)) return 8;
+  return wave_capable(d, elem, 16) ? 16 : 8;
 }
 
 size_t wave_lds(int B, int M, size_t elem) {
   return round256((size_t)B * fm::fft_line_stride(M) * 2 * elem);
 }
 
-// Pass d in the per-wavefront kernel with W (1, 2 or 4) wavefronts per workgroup; false
-// if it cannot run there.  comp_tiles: tiles per (b, c) tile position (ncomp, or 1 for
-// the three-component curl).
-bool set_wave(fm::PassDesc* d, size_t elem, int W, int comp_tiles) {
-  if (!wave_capable(*d, elem) || (W != 1 && W != 2 && W != 4)) return false;
-  const int B = W * fm::wave_lines(d->M);
+// Pass d in the per-wavefront kernel with E values per lane and W (1, 2 or 4) wavefronts
+// per workgroup; false if it cannot run there.  comp_tiles: tiles per (b, c) tile
+// position (ncomp, or 1 for the three-component curl).
+bool set_wave(fm::PassDesc* d, size_t elem, int W, int comp_tiles, int E) {
+  if (!wave_capable(*d, elem, E) || (W != 1 && W != 2 && W != 4)) return false;
+  const int B = W * fm::wave_lines(d->M, E);
   const size_t lds = wave_lds(B, d->M, elem);
   if (lds > (size_t)fm::kMaxLds) return false;
-  d->wave = 1;
+  d->wave = E;
   d->B = B;
   d->lds_bytes = (int)lds;
   d->raw_off = d->g_off = d->tab_off = 0;
@@ -515,15 +533,57 @@ int make_tables_and_green(fm_plan_s* p, hipStream_t st, bool deferred) {
 
   // stage twiddles of the per-wavefront kernel (the fused pass may run there, now or
   // after tuning)
-  if (wave_capable(p->pass[2], p->elem)) {
+  for (const int E : {16, 8}) {
+    if (!wave_capable(p->pass[2], p->elem, E)) continue;
     const int M = p->pass[2].M;
     void* ptr = nullptr;
-    const size_t n = (size_t)std::max(1, fm::wave_tw_size(M));
+    const size_t n = (size_t)std::max(1, fm::wave_tw_size(M, E));
     if (hipMalloc(&ptr, sizeof(T) * 2 * n) != hipSuccess) return FM_E_NOMEM;
-    p->wtw[M] = ptr;
+    p->wtw[E] = ptr;
     p->table_bytes += sizeof(T) * 2 * n;
-    FM_HIP(fm::launch_wave_twiddles<T>(ptr, M, st));
-    p->pass[2].wtw = ptr;
+    FM_HIP(fm::launch_wave_twiddles<T>(ptr, M, E, st));
+    (E == 16 ? p->pass[2].wtw : p->pass[2].wtw8) = ptr;
+  }
+
+  // the curl's derivative factor of every DFT mode k (signed k_s) of the three directions
+  // of the fused pass, in FP64, rounded once: the wavenumber 2 pi k_s / period (0 at the
+  // Nyquist mode), or the central-difference symbol (1/h) sum_j c_j sin(2 pi j k_s / M)
+  if (p->pass[2].g.curl) {
+    fm::GreenRef& g = p->pass[2].g;
+    const int order = g.deriv;
+    const int axes[3] = {g.axis_line, g.axis_b, g.axis_c};
+    const int Ms[3] = {g.M_line, g.M_b, g.M_c};
+    const double dws[3] = {g.dw_line, g.dw_b, g.dw_c};
+    std::vector<T> host;
+    size_t offs[3];
+    for (int t = 0; t < 3; ++t) {
+      offs[t] = host.size();
+      const double ih = 1.0 / p->ax[axes[t]].h;
+      const int M = Ms[t];
+      for (int k = 0; k < M; ++k) {
+        const long long ks = (2 * k > M) ? k - M : k;
+        auto sn = [&](int j) {  // sin(2 pi j ks / M), the angle reduced exactly
+          long long num = (2LL * j * ks) % (2LL * M);
+          if (num < 0) num += 2LL * M;
+          return std::sin(M_PI * (double)num / (double)M);
+        };
+        double v;
+        if (order == 0) v = (2 * k == M) ? 0.0 : dws[t] * (double)ks;
+        else if (order == 2) v = ih * sn(1);
+        else if (order == 4) v = ih * (4.0 / 3.0 * sn(1) - 1.0 / 6.0 * sn(2));
+        else v = ih * (1.5 * sn(1) - 0.3 * sn(2) + sn(3) / 30.0);
+        host.push_back(T(v));
+      }
+    }
+    void* ptr = nullptr;
+    if (hipMalloc(&ptr, sizeof(T) * host.size()) != hipSuccess) return FM_E_NOMEM;
+    p->dtab = ptr;
+    p->table_bytes += sizeof(T) * host.size();
+    FM_HIP(hipMemcpy(ptr, host.data(), sizeof(T) * host.size(), hipMemcpyHostToDevice));
+    T* base = reinterpret_cast<T*>(ptr);
+    g.dtab_line = base + offs[0];
+    g.dtab_b = base + offs[1];
+    g.dtab_c = base + offs[2];
   }
 
   // Green's spectrum: sample (FP64) -> DCT-I along convolution directions -> scale
@@ -654,6 +714,7 @@ void free_plan(fm_plan_s* p) {
   for (auto& kv : p->tw) (void)hipFree(kv.second);
   for (auto& kv : p->stw) (void)hipFree(kv.second);
   for (auto& kv : p->wtw) (void)hipFree(kv.second);
+  if (p->dtab) (void)hipFree(p->dtab);
   if (p->G) (void)hipFree(p->G);
   if (p->dpass) (void)hipFree(p->dpass);
   if (p->ws_internal) (void)hipFree(p->ws_internal);
@@ -696,8 +757,9 @@ bool wave_in_bounds(const fm::PassDesc& d, int64_t in_size, int64_t out_size, si
   auto span = [](int nc, int64_t sc, int nb, int64_t sb, int n, int64_t sl) {
     return (int64_t)(nc - 1) * sc + (int64_t)(nb - 1) * sb + (int64_t)(n - 1) * sl;
   };
-  if (!wave_capable(d, elem) || d.has_fix) return false;
-  const int L = fm::wave_lines(d.M);
+  const int E = d.wave;
+  if (!wave_capable(d, elem, E) || d.has_fix) return false;
+  const int L = fm::wave_lines(d.M, E);
   if (L < 1) return false;
   const int W = d.B / L;
   if (d.B % L || (W != 1 && W != 2 && W != 4)) return false;
@@ -942,9 +1004,6 @@ int build_plan(fm_plan_s* p) {
     g.M_c = p->ax[a0].M;
     g.deriv = p->kind == FM_BIOT_SAVART_FD2 ? 2 : p->kind == FM_BIOT_SAVART_FD4 ? 4
             : p->kind == FM_BIOT_SAVART_FD6 ? 6 : 0;
-    g.ih_line = 1.0 / A.h;
-    g.ih_b = 1.0 / p->ax[a1].h;
-    g.ih_c = 1.0 / p->ax[a0].h;
   }
   // pass 4: L2 -> L1 along a1 (inverse of pass 2)
   {
@@ -1041,12 +1100,13 @@ int build_plan(fm_plan_s* p) {
     if (rc2) return rc2;
     d.tiles = ((d.nb + d.B - 1) / d.B) * d.nc * (fused_curl ? 1 : p->ncomp);
     set_magics(&d);
-    if (i == 2 && wave_capable(d, p->elem)) {
+    if (i == 2 && wave_capable(d, p->elem) && !(fused_curl && p->elem == 8)) {
       // the per-wavefront kernel, with the most wavefronts per workgroup whose LDS stays
       // within the preferred size
+      const int E = default_wave_values(d, p->elem);
       for (const int W : {4, 2, 1}) {
         fm::PassDesc w = d;
-        if (set_wave(&w, p->elem, W, fused_curl ? 1 : p->ncomp) && w.lds_bytes <= fm::kSoftLds) {
+        if (set_wave(&w, p->elem, W, fused_curl ? 1 : p->ncomp, E) && w.lds_bytes <= fm::kSoftLds) {
           d = w;
           break;
         }
@@ -1093,7 +1153,8 @@ int launch_one(fm_plan_s* p, int i, const void* in, void* out, hipStream_t st) {
                  d.M, p->prec == FM_F64 ? "f64" : "f32", d.tiles, d.B, d.lds_bytes);
     std::fflush(stderr);
   }
-  if (d.wave && !d.wtw) return FM_E_ARG;
+  if (d.wave && !(d.wave == 16 ? d.wtw : d.wtw8)) return FM_E_ARG;
+  if (d.fused && d.g.curl && !(d.g.dtab_line && d.g.dtab_b && d.g.dtab_c)) return FM_E_ARG;
   hipError_t e = (p->prec == FM_F64) ? fm::launch_pass<double>(d, p->dpass + i, in, out, st)
                                      : fm::launch_pass<float>(d, p->dpass + i, in, out, st);
   if (e == hipSuccess && sync_debug()) e = hipStreamSynchronize(st);
@@ -1569,7 +1630,7 @@ int fm_solve_batched(int count, const fm_plan* plans, const void* const* rhs_dev
 // tables, 0 one tile per workgroup with LDS tables, 2 one tile per workgroup with global
 // tables (the only mode of the runtime-length and long FP64 kernels).
 int launch_mode(const fm::PassDesc& d, size_t elem) {
-  if (d.wave) return 3;
+  if (d.wave) return d.wave == 16 ? 3 : 4;
   const bool pipelined = compile_time_kernel(d, elem) && fm::pipelined_kernel((int)elem, d.M);
   if (!pipelined || !d.lds_tabs) return 2;
   return d.persist ? 1 : 0;
@@ -1585,12 +1646,15 @@ bool retile(const fm_plan_s* p, int i, int bmax, int mode, fm::PassDesc* out) {
   const int64_t sizes_in[5] = {p->Vu, p->V1, p->V2, p->V2, p->V1};
   const int64_t sizes_out[5] = {p->V1, p->V2, p->V2, p->V1, p->Vu};
   d.wave = 0;
-  if (mode == 3) {
-    // the per-wavefront kernel: the most wavefronts per workgroup within bmax lines
-    if (!wave_capable(d, p->elem)) return false;
+  if (mode == 3 || mode == 4) {
+    // the per-wavefront kernel (16 or 8 values per lane): the most wavefronts per
+    // workgroup within bmax lines
+    const int E = mode == 3 ? 16 : 8;
+    if (!wave_capable(d, p->elem, E)) return false;
     for (const int W : {4, 2, 1}) {
       fm::PassDesc w = d;
-      if (W * fm::wave_lines(d.M) > bmax || !set_wave(&w, p->elem, W, fused_curl ? 1 : p->ncomp)) continue;
+      if (W * fm::wave_lines(d.M, E) > bmax || !set_wave(&w, p->elem, W, fused_curl ? 1 : p->ncomp, E))
+        continue;
       if (!pass_in_bounds(w, sizes_in[i], sizes_out[i], p->elem)) return false;
       *out = w;
       return true;
@@ -1657,7 +1721,7 @@ int fm_plan_tune(fm_plan p, void* workspace_dev, void* hip_stream) {
     he = time_pass(i, best, &best_ms);
     std::vector<std::pair<int, int>> seen{{best.B, launch_mode(best, p->elem)}};
     for (const int bmax : {64, 32, 16, 8, 4, 2, 1}) {
-      for (const int mode : {1, 0, 2, 3}) {
+      for (const int mode : {1, 0, 2, 3, 4}) {
         fm::PassDesc d;
         if (he != hipSuccess || !retile(p, i, bmax, mode, &d)) continue;
         const std::pair<int, int> key{d.B, launch_mode(d, p->elem)};
@@ -1708,7 +1772,7 @@ int fm_plan_set_tiling(fm_plan p, const int lines_per_tile[5], const int persist
   fm::PassDesc next[5];
   for (int i = 0; i < 5; ++i) {
     const int mode = persist[i];
-    if (lines_per_tile[i] < 1 || mode < 0 || mode > 3) return FM_E_ARG;
+    if (lines_per_tile[i] < 1 || mode < 0 || mode > 4) return FM_E_ARG;
     if (!retile(p, i, lines_per_tile[i], mode, &next[i])) return FM_E_ARG;
     // exactly the requested tiling (retile takes the largest tile up to the bound)
     if (next[i].B != lines_per_tile[i] || launch_mode(next[i], p->elem) != mode) return FM_E_ARG;

@@ -18,9 +18,9 @@
 
 namespace fm {
 
-template <typename T, int M>
+template <typename T, int M, int E_>
 struct WaveShape {
-  static constexpr int E = kWaveValues;
+  static constexpr int E = E_;
   static constexpr int P = M / E;
   static constexpr int L = 64 / P;
 };
@@ -39,18 +39,16 @@ __device__ __forceinline__ void wave_lds_sync() {
 // holds input r of the lane's butterfly i (t = j + P i), i.e. point t + r M / R; the
 // first stage's inputs are the lane layout itself (one butterfly, t = j).  After the
 // last stage v[m] holds output j + P m.
-template <typename T, int M, int s, int S>
-__device__ __forceinline__ void wave_stages(cpx<T> (&v)[kWaveValues], int j, cpx<T>* buf,
-                                            GTab<T> tw) {
-  constexpr int E = kWaveValues;
+template <typename T, int M, int E, int s, int S>
+__device__ __forceinline__ void wave_stages(cpx<T> (&v)[E], int j, cpx<T>* buf, GTab<T> tw) {
   constexpr int P = M / E;
-  constexpr int R = wave_radix(M, s);
+  constexpr int R = wave_radix(M, s, E);
   if constexpr (R != 0) {
-    constexpr int Ns = wave_ns(M, s);
+    constexpr int Ns = wave_ns(M, s, E);
     constexpr int NB = E / R;  // butterflies per lane
     if constexpr (s > 0) {
       // W_{Ns R}^{k r}, k = t mod Ns (table: offset + (r - 1) Ns + k)
-      constexpr int off = wave_tw_offset(M, s);
+      constexpr int off = wave_tw_offset(M, s, E);
 #pragma unroll
       for (int i = 0; i < NB; ++i) {
         const int k = (j + P * i) & (Ns - 1);
@@ -64,7 +62,7 @@ __device__ __forceinline__ void wave_stages(cpx<T> (&v)[kWaveValues], int j, cpx
     }
 #pragma unroll
     for (int i = 0; i < NB; ++i) SmallDft<R, S, T>::run(&v[i * R]);
-    constexpr int R2 = wave_radix(M, s + 1);
+    constexpr int R2 = wave_radix(M, s + 1, E);
     if constexpr (R2 == 0) {
       // last stage: output q of butterfly i is point t + q Ns = j + P (i + NB q)
       cpx<T> nat[E];
@@ -95,17 +93,17 @@ __device__ __forceinline__ void wave_stages(cpx<T> (&v)[kWaveValues], int j, cpx
 #pragma unroll
         for (int r = 0; r < R2; ++r) v[i * R2 + r] = buf[pad16(t + r * MR2)];
       }
-      wave_stages<T, M, s + 1, S>(v, j, buf, tw);
+      wave_stages<T, M, E, s + 1, S>(v, j, buf, tw);
     }
   }
 }
 
 // One tile of the fused pass: W wavefronts of L lines each.  KIND is K_F_C2C (Poisson:
 // times the Green's spectrum) or K_F_CURL (three components per line: u = G i w x f).
-template <typename T, int M, int KIND>
+template <typename T, int M, int KIND, int EV>
 __device__ __forceinline__ void wave_tile(const PassDesc& d, const void* in, void* out, char* smem,
                                           int tile) {
-  using WS = WaveShape<T, M>;
+  using WS = WaveShape<T, M, EV>;
   constexpr int E = WS::E, P = WS::P, L = WS::L;
   constexpr int NCL = KIND == K_F_CURL ? 3 : 1;
   const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
@@ -114,7 +112,7 @@ __device__ __forceinline__ void wave_tile(const PassDesc& d, const void* in, voi
   const TileIdx ti = tile_index(d, tile);
   if (l >= ti.nl) return;  // no workgroup barrier follows
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem) + (size_t)(wave * L + lane / P) * fft_line_stride(M);
-  const GTab<T> tw = gptr<cpx<T>>(d.wtw);
+  const GTab<T> tw = gptr<cpx<T>>(E == 16 ? d.wtw : d.wtw8);
   const int b = ti.b0 + l;
   const int comp0 = NCL == 3 ? 0 : ti.comp;
   const int64_t line_off = (int64_t)ti.c * d.in_s_c + (int64_t)b * d.in_s_b;
@@ -141,16 +139,14 @@ __device__ __forceinline__ void wave_tile(const PassDesc& d, const void* in, voi
         v[q][m] = cpx<T>{z.x, z.y};
       }
     }
-    wave_stages<T, M, 0, -1>(v[q], j, buf, tw);
+    wave_stages<T, M, E, 0, -1>(v[q], j, buf, tw);
   }
   if constexpr (KIND == K_F_CURL) {
-    const T wc = curl_wave<T>(ti.c, d.g.M_c, T(d.g.dw_c), T(d.g.ih_c), d.g.deriv);
-    const T wb = curl_wave<T>(b, d.g.M_b, T(d.g.dw_b), T(d.g.ih_b), d.g.deriv);
-    const T ihl = T(d.g.ih_line);
-    const T dwl = T(d.g.dw_line);
+    const T wc = curl_wave<T>(ti.c, d.g.dtab_c);
+    const T wb = curl_wave<T>(b, d.g.dtab_b);
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-      const T wl = curl_wave<T>(j + P * m, d.g.M_line, dwl, ihl, d.g.deriv);
+      const T wl = curl_wave<T>(j + P * m, d.g.dtab_line);
       const T wx = d.g.axis_line == 0 ? wl : (d.g.axis_b == 0 ? wb : wc);
       const T wy = d.g.axis_line == 1 ? wl : (d.g.axis_b == 1 ? wb : wc);
       const T wz = d.g.axis_line == 2 ? wl : (d.g.axis_b == 2 ? wb : wc);
@@ -169,7 +165,7 @@ __device__ __forceinline__ void wave_tile(const PassDesc& d, const void* in, voi
   }
 #pragma unroll
   for (int q = 0; q < NCL; ++q) {
-    wave_stages<T, M, 0, +1>(v[q], j, buf, tw);
+    wave_stages<T, M, E, 0, +1>(v[q], j, buf, tw);
     auto* dst = (__attribute__((address_space(1))) cpx<T>*)(out) +
                 (int64_t)(comp0 + q) * d.out_s_comp + (int64_t)ti.c * d.out_s_c + (int64_t)b * d.out_s_b;
 #pragma unroll
@@ -185,20 +181,23 @@ __device__ __forceinline__ void wave_tile(const PassDesc& d, const void* in, voi
 
 // Tiles in the XCD-aware order of the other pass kernels; a grid of one workgroup per
 // tile gives each workgroup one or two tiles.
-template <int KIND>
+// Occupancy targets of the three-component (curl) kernels: 16 values per lane need the
+// 256 VGPRs of two waves per SIMD; 8 FP32 values fit the 168 of three (FP64 would spill
+// there and keeps the compiler's choice).
+template <typename T, int KIND, int E>
 constexpr int wave_min_waves() {
-  return KIND == K_F_CURL ? 2 : 1;  // three-component lines: up to 256 VGPRs
+  return KIND == K_F_CURL ? (E == 16 ? 2 : (sizeof(T) == 4 ? 3 : 1)) : 1;
 }
 
-template <typename T, int M, int KIND>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(wave_min_waves<KIND>())))
+template <typename T, int M, int KIND, int E>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(wave_min_waves<T, KIND, E>())))
 void wave_pass_kernel(const PassDesc* __restrict__ dp, const void* in, void* out) {
   extern __shared__ __align__(16) char smem[];
   const PassDesc& d = *dp;
   for (int k = 0;; ++k) {
     const int tile = xcd_tile(blockIdx.x, gridDim.x, k, d.tiles);
     if (tile < 0) return;
-    wave_tile<T, M, KIND>(d, in, out, smem, tile);
+    wave_tile<T, M, KIND, E>(d, in, out, smem, tile);
   }
 }
 

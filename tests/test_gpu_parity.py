@@ -189,23 +189,22 @@ def test_batched_bitwise_equals_single(prec):
 @pytest.mark.parametrize("prec,tol", [(F.F64, TOL64), (F.F32, TOL32)])
 @pytest.mark.parametrize("M", [32, 64, 128, 256, 512, 1024])
 def test_per_wavefront_fused_kernel(M, prec, tol):
-    """The per-wavefront fused kernel (launch mode 3) at every power-of-two line length it
-    serves, with 1, 2 and 4 wavefronts per workgroup (ragged last tiles): unbounded and
-    periodic last axes, both layouts, two right-hand sides per solve, and the spectral
-    curl (FP32)."""
+    """The per-wavefront fused kernel at every power-of-two line length it serves, with 16
+    values per lane (launch mode 3) and 8 (mode 4, lines of at most 512), 1, 2 and 4
+    wavefronts per workgroup (ragged last tiles): unbounded and periodic last axes, both
+    layouts, two right-hand sides per solve, and the spectral curl."""
     rng = np.random.default_rng(M + 7 * prec)
     cases = [([6, 5, M // 2], [[3, 3], [0, 1], [3, 3]], F.CELL, F.POISSON, 2),
              ([7, 6, M // 2], [[1, 3], [2, 2], [3, 3]], F.NODE, F.POISSON, 1),
              ([5, 6, M], [[2, 2], [1, 0], [2, 2]], F.NODE, F.POISSON, 1)]
-    if prec == F.F32:
+    if prec == F.F32 or M <= 512:
         cases.append(([6, 5, M // 2], [[3, 3], [2, 2], [3, 3]], F.CELL, F.BIOT_SAVART, 3))
         cases.append(([5, 6, M], [[2, 2], [2, 2], [2, 2]], F.NODE, F.BIOT_SAVART, 3))
     h = [0.11, 0.09, 1.0 / M]
     for n, bc, layout, kind, ncomp in cases:
         plan = F.Plan(n, h, bc, layout, F.CHAT2, prec, kind, ncomp)
         t = plan.tiling()
-        assert t["persistent"][2] == 3, (n, bc, t)
-        lines = 64 // (M // 16)
+        assert t["persistent"][2] in ((3, 4) if (prec == F.F32 or kind == F.POISSON) else (0, 1, 2)), (n, bc, t)
         shape = ((ncomp,) if ncomp > 1 else ()) + O.user_shape(n, layout)
         f = rng.standard_normal(shape)
         if kind == F.BIOT_SAVART:
@@ -213,19 +212,24 @@ def test_per_wavefront_fused_kernel(M, prec, tol):
         else:
             ref = np.stack([oracle_solve(f[c] if ncomp > 1 else f, n, h, bc, layout) for c in range(ncomp)])
             ref = ref if ncomp > 1 else ref[0]
-        for waves in (1, 2, 4):
-            b = list(t["lines_per_tile"])
-            q = list(t["persistent"])
-            b[2], q[2] = waves * lines, 3
-            try:
-                plan.set_tiling(b, q)
-            except F.FluxmiError:
-                assert prec == F.F64 and M * waves * lines * 16 > 160 * 1024, (M, waves)
+        ran = 0
+        for values, mode in ((16, 3), (8, 4)):
+            if M // values > 64 or M < 2 * values:
                 continue
-            u = gpu_solve(plan, f)
-            check_conventions(u, bc, layout)
-            err = rel_linf(u, ref)
-            assert err < tol, (M, n, bc, layout, kind, waves, err)
+            if kind == F.BIOT_SAVART and prec == F.F64 and values == 16:
+                continue  # not built: three 16-value FP64 lines per lane
+            lines = 64 // (M // values)
+            for waves in (1, 2, 4):
+                b = list(t["lines_per_tile"])
+                q = list(t["persistent"])
+                b[2], q[2] = waves * lines, mode
+                plan.set_tiling(b, q)
+                u = gpu_solve(plan, f)
+                check_conventions(u, bc, layout)
+                err = rel_linf(u, ref)
+                assert err < tol, (M, n, bc, layout, kind, values, waves, err)
+                ran += 1
+        assert ran >= 3
         plan.close()
 
 
@@ -234,7 +238,7 @@ def test_per_wavefront_fused_kernel(M, prec, tol):
 def test_biot_savart_finite_difference(kind, prec, tol):
     """The curl with the central-difference symbols of order 2, 4, 6 (Sec. V), periodic
     and unbounded axes, both layouts; a power-of-two last axis runs the per-wavefront
-    kernel (FP32) and, re-tiled, the LDS-tile kernel."""
+    kernel and, re-tiled, the LDS-tile kernel."""
     for layout in (F.CELL, F.NODE):
         for bc in ([[3, 3]] * 3, [[2, 2], [3, 3], [3, 3]], [[3, 3], [2, 2], [2, 2]], [[2, 2]] * 3):
             err = _case([12, 10, 14], [0.1, 0.12, 0.09], bc, layout, prec, 5, kind=kind)
@@ -258,4 +262,5 @@ def test_biot_savart_finite_difference(kind, prec, tol):
         err = rel_linf(gpu_solve(plan, f), ref)
         assert err < tol, (mode, err)
     plan.close()
-    assert (3 in modes) == (prec == F.F32) and len(modes) >= 2, modes
+    # the planner's choice: 8 values per lane (FP32), the LDS-tile kernel (FP64)
+    assert (modes[0] == 4) == (prec == F.F32) and len(modes) >= 2, modes
