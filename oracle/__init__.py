@@ -11,7 +11,8 @@ spectrum (Eq. of Sec. II) or by the Green's spectrum times the spectral curl (Se
 
 Boundary codes: 0 even, 1 odd, 2 periodic, 3 unbounded.  Layout: 0 cell, 1 node.
 Green: 0 CHAT2 as printed in Sec. IV (sphere-mean self-term times the cell volume),
-1 the sphere-mean self-term itself.  Kind: 0 Poisson, 1 Biot-Savart (spectral curl),
+1 the sphere-mean self-term itself, 2..6 the regularised HEJ2..HEJ10 kernels, 7 HEJ0
+(the HEJ kernels with three convolution directions or none).  Kind: 0 Poisson, 1 Biot-Savart (spectral curl),
 2 / 3 / 4 Biot-Savart with the finite-difference curl of order 2 / 4 / 6.
 """
 from __future__ import annotations

@@ -439,12 +439,79 @@ void axis_backward(const Axis& a, const cd* in, cd* out, int mode) {
 //   d_u = 2, k = 0:  (pi - 6 + 2 ln(pi r_eq^2 / 2)) / (8 pi), the corrected expression
 //            of the footnote in Sec. V (the square-cell mean of ln(rho)/(2 pi)),
 //   d_u = 2, k > 0:  the mean of -K0(k rho)/(2 pi) over the disc of area hx*hy.
+// Regularised kernels (Sec. IV names them HEJ2 ... HEJ10 and HEJ0 after Hejlesen et al.;
+// their formulas are in that work, not in the paper).  Order m = 2 q + 2 smooths the
+// point source with the Gaussian-Laguerre function
+//   zeta_m(x) = (2 pi eps^2)^(-3/2) exp(-rho^2 / 2) L_q^(3/2)(rho^2 / 2),  rho = |x| / eps,
+// whose moments vanish up to order m; its Fourier transform is
+//   exp(-s) sum_{j < m/2} s^j / j!,  s = (k eps)^2 / 2.
+// The kernel -(1/4 pi r) * [erf(rho / sqrt 2) + sqrt(2/pi) rho exp(-rho^2/2) P_m(rho^2)]
+// solves lap G = zeta_m (P_m below follows from integrating the radial equation
+// twice); its origin value is -sqrt(2/pi) c_m / (4 pi eps).  HEJ0 cuts the spectrum off
+// at the sphere |k| <= pi / h: G = -Si(pi r / h) / (2 pi^2 r), G(0) = -1 / (2 pi h).
+// With eps = 2 h these reproduce the printed convergence of every HEJ kernel.
+const double kHejPoly[5][4] = {{0, 0, 0, 0},
+                               {0.5, 0, 0, 0},
+                               {7.0 / 8.0, -1.0 / 8.0, 0, 0},
+                               {19.0 / 16.0, -1.0 / 3.0, 1.0 / 48.0, 0},
+                               {187.0 / 128.0, -233.0 / 384.0, 29.0 / 384.0, -1.0 / 384.0}};
+const double kHejOrigin[5] = {1.0, 1.5, 15.0 / 8.0, 35.0 / 16.0, 315.0 / 128.0};
+
+// Gauss-Legendre nodes and weights on [-1, 1] (Newton's method on P_n).
+void gauss_legendre(int n, std::vector<double>* x, std::vector<double>* w) {
+  x->resize(n);
+  w->resize(n);
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(kPi * (i + 0.75) / (n + 0.5)), dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    (*x)[i] = z;
+    (*w)[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+// Si(x) = int_0^x sin(t)/t dt, x >= 0, by 24-point Gauss-Legendre on panels [j pi,
+// (j+1) pi] (whole panels summed once and cached) plus the last partial panel.
+double sine_integral(double x) {
+  static std::mutex mu;
+  static std::vector<double> gx, gw, prefix{0.0};
+  auto panel = [&](double a, double b) {
+    double acc = 0.0;
+    for (size_t i = 0; i < gx.size(); ++i) {
+      const double t = 0.5 * (a + b) + 0.5 * (b - a) * gx[i];
+      acc += gw[i] * std::sin(t) / t;
+    }
+    return 0.5 * (b - a) * acc;
+  };
+  std::lock_guard<std::mutex> lock(mu);
+  if (gx.empty()) gauss_legendre(24, &gx, &gw);
+  const long j = (long)(x / kPi);
+  while ((long)prefix.size() <= j) {
+    const long m = (long)prefix.size() - 1;
+    prefix.push_back(prefix.back() + panel(m * kPi, (m + 1) * kPi));
+  }
+  return prefix[j] + (x > j * kPi ? panel(j * kPi, x) : 0.0);
+}
+
 struct Green {
   int du = 0;
   int variant = 0;
   double cellvol = 1.0;  // product of h over the convolution directions
   double r_eq = 0.0;
+  double eps = 0.0;      // HEJ2..10: regularisation length 2 h
+  double kc = 0.0;       // HEJ0: spectral cut-off pi / h
   double value(double rho, double k) const {
+    if (variant >= 2) return hej(rho, k);
     if (du == 3) {
       if (rho > 0) return -1.0 / (4.0 * kPi * rho);
       const double s = -3.0 / (8.0 * kPi * r_eq);
@@ -464,6 +531,33 @@ struct Green {
       return -std::exp(-k * rho) / (2.0 * k);
     }
     return (k == 0.0) ? 0.0 : -1.0 / (k * k);
+  }
+  // variant 2..6: HEJ2..HEJ10; variant 7: HEJ0.  Three convolution directions (mixed
+  // space = real space) or none (spectral); the mixed forms are not built.
+  double hej(double r, double k) const {
+    const int q = variant - 2;  // 0..4 for HEJ2..HEJ10
+    if (du == 3) {
+      if (variant == 7) {
+        if (r > 0) return -sine_integral(kc * r) / (2.0 * kPi * kPi * r);
+        return -kc / (2.0 * kPi * kPi);
+      }
+      const double c = std::sqrt(2.0 / kPi);
+      if (r == 0.0) return -c * kHejOrigin[q] / (4.0 * kPi * eps);
+      const double p = r / eps, p2 = p * p;
+      double poly = 0.0;
+      for (int i = 3; i >= 0; --i) poly = poly * p2 + kHejPoly[q][i];
+      return -(std::erf(p / std::sqrt(2.0)) + c * p * std::exp(-0.5 * p2) * poly) / (4.0 * kPi * r);
+    }
+    // spectral: -zeta_hat(k) / k^2
+    if (k == 0.0) return 0.0;
+    if (variant == 7) return k <= kc ? -1.0 / (k * k) : 0.0;
+    const double sv = 0.5 * (k * eps) * (k * eps);
+    double term = 1.0, sum = 1.0;
+    for (int j = 1; j <= q; ++j) {
+      term *= sv / j;
+      sum += term;
+    }
+    return -std::exp(-sv) * sum / (k * k);
   }
 };
 
@@ -511,7 +605,7 @@ int make_problem(const int* n, const double* h, const int* bc, int layout, int g
     const int rc = make_axis(n[a], h[a], layout, bc[2 * a], bc[2 * a + 1], &P->ax[a]);
     if (rc) return rc;
   }
-  if (green != 0 && green != 1) return -3;
+  if (green < 0 || green > 7) return -3;
   if (kind < 0 || kind > 4) return -3;
   P->kind = kind;
   if (kind >= 1)
@@ -526,6 +620,14 @@ int make_problem(const int* n, const double* h, const int* bc, int layout, int g
   P->g.cellvol = vol;
   if (P->du == 3) P->g.r_eq = std::cbrt(3.0 * vol / (4.0 * kPi));
   if (P->du == 2) P->g.r_eq = std::sqrt(vol / kPi);
+  if (green >= 2) {
+    // regularised kernels: three convolution directions or none; the grid spacing is
+    // the cube root of the cell volume (the spacing itself on isotropic grids)
+    if (P->du == 1 || P->du == 2) return -3;
+    const double hc = std::cbrt(P->ax[0].h * P->ax[1].h * P->ax[2].h);
+    P->g.eps = 2.0 * hc;
+    P->g.kc = kPi / hc;
+  }
   return 0;
 }
 
@@ -917,6 +1019,10 @@ double oracle_green_value(int du, int variant, double cellvol, double rho, doubl
   g.cellvol = cellvol;
   if (du == 3) g.r_eq = std::cbrt(3.0 * cellvol / (4.0 * kPi));
   if (du == 2) g.r_eq = std::sqrt(cellvol / kPi);
+  if (variant >= 2) {  // HEJ: h = cellvol^(1/3)
+    g.eps = 2.0 * std::cbrt(cellvol);
+    g.kc = kPi / std::cbrt(cellvol);
+  }
   return g.value(rho, k);
 }
 
