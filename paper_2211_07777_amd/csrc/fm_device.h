@@ -776,10 +776,10 @@ __device__ void plain_compute(const PassDesc& d, void* out, const TileIdx& ti, c
     }
     fft_lines<T, MC, +1>(buf, ls, F, d, tb.stw, g, scatter == S_REAL2 ? min(d.out_n, M) : M);
   } else {
+    // the first stage builds the symmetric extension as it reads the raw tile (every
+    // read of a stage precedes its writes, so the raw tile may alias the FFT buffer)
     GatherR2R<T, P> g{reinterpret_cast<const T*>(smem + d.raw_off), rs, d.in_n, nl, d.r2r, tw};
-    extend_r2r<T, MC>(buf, ls, F, M, g);
-    auto lds = [buf, ls](int line, int idx) { return buf[line * ls + pad16(idx)]; };
-    fft_lines<T, MC, -1>(buf, ls, F, d, tb.stw, lds);
+    fft_lines<T, MC, -1>(buf, ls, F, d, tb.stw, g);
   }
 
   // 3) write the lines into the output layout

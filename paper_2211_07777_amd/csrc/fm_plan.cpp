@@ -293,10 +293,10 @@ void set_magics(fm::PassDesc* d) {
 bool pass_in_bounds(const fm::PassDesc& d, int64_t in_size, int64_t out_size, size_t elem);
 int64_t tile_in_span_bytes(const fm::PassDesc& d, size_t elem);
 
-// LDS layout of one tile: the FFT buffer and the raw input tile (real-to-real tiles
-// keep the raw tile, and the fused real spectrum, after the buffer), then the fused
-// tile's Green rows at g_off, then the twiddle tables of the persistent kernels at
-// tab_off.  Returns the total bytes.
+// LDS layout of one tile: the FFT buffer and the raw input tile (the raw tile aliases the
+// buffer, except for fused real-to-real tiles, which keep it and their real spectrum
+// after the buffer), then the fused tile's Green rows at g_off, then the twiddle tables
+// of the persistent kernels at tab_off.  Returns the total bytes.
 struct TileLds {
   size_t raw_off, g_off, tab_off, total;
 };
@@ -309,11 +309,9 @@ TileLds tile_lds(const fm::PassDesc& d, int B, size_t elem, int comps, bool fuse
   const size_t raw = (size_t)comps * B * (d.in_n + 1) * in_elem;
   TileLds t{};
   size_t end;
-  if (d.gather == fm::G_R2R) {
+  if (d.gather == fm::G_R2R && fused_r2r) {
     t.raw_off = round256(fft);
-    size_t extra = raw;
-    if (fused_r2r) extra = std::max(extra, (size_t)B * (d.spec_n + 1) * elem);
-    end = t.raw_off + extra;
+    end = t.raw_off + std::max(raw, (size_t)B * (d.spec_n + 1) * elem);
   } else {
     end = std::max(fft, raw);
   }
@@ -830,10 +828,9 @@ bool pass_in_bounds(const fm::PassDesc& d, int64_t in_size, int64_t out_size, si
   const size_t fft = (size_t)F * fm::fft_line_stride(M) * 2 * elem;
   const size_t raw = (size_t)comps * d.B * (d.in_n + 1) * (d.in_cplx ? 2 : 1) * elem;
   size_t need = std::max(fft, raw);
-  if (d.gather == fm::G_R2R) {
+  if (d.gather == fm::G_R2R && d.fused) {
     if ((size_t)d.raw_off < fft) return false;
-    need = d.raw_off + raw;
-    if (d.fused) need = std::max(need, d.raw_off + (size_t)d.B * (d.spec_n + 1) * elem);
+    need = std::max(d.raw_off + raw, d.raw_off + (size_t)d.B * (d.spec_n + 1) * elem);
   } else if (d.raw_off != 0) {
     return false;
   }
