@@ -550,7 +550,9 @@ struct Green {
     }
     // spectral: -zeta_hat(k) / k^2
     if (k == 0.0) return 0.0;
-    if (variant == 7) return k <= kc ? -1.0 / (k * k) : 0.0;
+    // modes on the cut-off sphere (the Nyquist modes of an even periodic grid lie on it)
+    // are kept: a relative margin keeps the rounding of |k| from deciding
+    if (variant == 7) return k <= kc * (1.0 + 1e-12) ? -1.0 / (k * k) : 0.0;
     const double sv = 0.5 * (k * eps) * (k * eps);
     double term = 1.0, sum = 1.0;
     for (int j = 1; j <= q; ++j) {

@@ -84,3 +84,72 @@ def test_origin_value_is_the_limit():
 def test_mixed_directions_are_refused():
     with pytest.raises(ValueError):
         O.solve(np.zeros((9, 9, 9)), [8] * 3, [0.1] * 3, [[3, 3], [3, 3], [2, 2]], O.NODE, 2, 0)
+
+
+def _zeta(q, eps):
+    """The Gaussian-Laguerre smoothing function of order 2 q + 2, from its Laguerre form."""
+    def z(r):
+        rho = r / eps
+        return (2 * np.pi * eps ** 2) ** -1.5 * np.exp(-rho ** 2 / 2) * \
+            special.eval_genlaguerre(q, 1.5, rho ** 2 / 2)
+    return z
+
+
+def _zeta_hat_quadrature(q, eps, k):
+    """Fourier transform of the radial function zeta by quadrature:
+    4 pi int zeta(r) r^2 sin(k r) / (k r) dr (independent of any closed form)."""
+    z = _zeta(q, eps)
+    if k == 0:
+        return integrate.quad(lambda r: 4 * np.pi * z(r) * r * r, 0, 14 * eps, epsabs=1e-14, epsrel=1e-12)[0]
+    return integrate.quad(lambda r: 4 * np.pi * z(r) * r * np.sin(k * r) / k, 0, 14 * eps,
+                          epsabs=1e-14, epsrel=1e-12, limit=200)[0]
+
+
+def test_smoothing_functions_have_unit_mass_and_vanishing_moments():
+    """The source written in these tests is the right one: unit mass, and the radial
+    moments int r^(2j) zeta d^3x vanish for 0 < 2 j < m (order m = 2 q + 2)."""
+    eps = 0.3
+    for q in range(5):
+        z = _zeta(q, eps)
+        for j in range(q + 1):
+            mom = integrate.quad(lambda r: 4 * np.pi * z(r) * r ** (2 * j + 2), 0, 16 * eps,
+                                 epsabs=1e-14, epsrel=1e-12)[0]
+            assert abs(mom - (1.0 if j == 0 else 0.0)) < 1e-10 * max(1.0, eps ** (2 * j)), (q, j, mom)
+        # and the next moment does not vanish (the order is exactly m)
+        mom = integrate.quad(lambda r: 4 * np.pi * z(r) * r ** (2 * q + 4), 0, 16 * eps,
+                             epsabs=1e-14, epsrel=1e-12)[0]
+        assert abs(mom) > 1e-3 * eps ** (2 * q + 2), q
+
+
+def test_spectral_form_on_a_periodic_grid_mode_by_mode():
+    """All-periodic node grid: a Fourier mode cos(k.x) comes back as
+    -zeta_hat(|k|) / |k|^2 times itself, with zeta_hat by quadrature of the Laguerre form
+    (HEJ2 ... HEJ10); HEJ0 returns -1/|k|^2 inside the sphere |k| <= pi / h and 0 outside."""
+    N, h = 16, 1 / 16
+    x = np.arange(N + 1) * h
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    for m in [(1, 0, 0), (2, 3, 1), (5, 5, 4), (8, 0, 0), (7, 6, 5)]:
+        kv = 2 * np.pi * np.array(m, dtype=float)
+        k = np.linalg.norm(kv)
+        f = np.cos(kv[0] * X + kv[1] * Y + kv[2] * Z + 0.3)
+        for v in range(2, 8):
+            u = O.solve(f, [N] * 3, [h] * 3, [[2, 2]] * 3, O.NODE, v, 0)
+            if v == 7:
+                mult = -1 / k ** 2 if k <= np.pi / h * (1 + 1e-12) else 0.0
+            else:
+                mult = -_zeta_hat_quadrature(v - 2, 2 * h, k) / k ** 2
+            assert np.abs(u - mult * f).max() < 1e-10 / k ** 2, (m, v)
+
+
+def test_far_field_is_the_point_source():
+    """Beyond the smoothing core the kernels are -1/(4 pi r) up to terms of order
+    rho^(m-1) exp(-rho^2 / 2): unit-source solve on a 24^3 node grid, r = 16 ... 24 h
+    (rho >= 8), to 1e-7 relative; inside the core (r = 2 h) they differ by far more."""
+    n, h = [24, 24, 24], [1 / 24] * 3
+    f = np.zeros(O.user_shape(n, O.NODE))
+    f[0, 0, 0] = 1.0 / np.prod(h)
+    r = np.arange(16, 25) * h[0]
+    for v in range(2, 7):
+        u = O.solve(f, n, h, [[3, 3]] * 3, O.NODE, v, 0)
+        assert np.abs(u[0, 0, 16:] * (4 * np.pi * r) + 1).max() < 1e-7, v
+        assert abs(u[0, 0, 2] * (4 * np.pi * 2 * h[0]) + 1) > 1e-2, v
