@@ -46,8 +46,29 @@ typedef enum { FM_CELL = 0, FM_NODE = 1 } fm_layout;
  *   FM_GREEN_CHAT2_VOL the same kernel with the plain equal-volume-sphere mean.
  * With two convolution directions both use, at the origin, the square-cell mean of
  * ln(rho)/(2 pi) (footnote of Sec. V) for the zero spectral wavenumber and the disc
- * mean of -K0(k rho)/(2 pi) otherwise. */
-typedef enum { FM_GREEN_CHAT2 = 0, FM_GREEN_CHAT2_VOL = 1 } fm_green;
+ * mean of -K0(k rho)/(2 pi) otherwise.
+ * Regularised kernels (Sec. IV, the HEJ family; their formulas come from the work the
+ * paper cites for them): the Green's function of a smoothed point source
+ *   FM_GREEN_HEJ2 ... FM_GREEN_HEJ10  order m = 2, 4, 6, 8, 10: the Gaussian-Laguerre
+ *                      source of width eps whose moments vanish up to order m,
+ *                      Fourier transform exp(-s) sum_{j < m/2} s^j / j!,
+ *                      s = (k eps)^2 / 2;
+ *   FM_GREEN_HEJ0      the spectrally truncated point source: wavenumbers with
+ *                      |k| <= pi / h kept, the rest cut off.
+ * eps = 2 h with h = (hx hy hz)^(1/3) (the reading that reproduces the printed errors of
+ * every HEJ kernel).  These need three unbounded directions (the real-space form
+ * -(1/4 pi r)[erf(r / (sqrt 2 eps)) + ...], finite at r = 0) or none (the spectral form
+ * -zeta_hat(k) / k^2); other mixes return FM_E_KIND. */
+typedef enum {
+  FM_GREEN_CHAT2 = 0,
+  FM_GREEN_CHAT2_VOL = 1,
+  FM_GREEN_HEJ2 = 2,
+  FM_GREEN_HEJ4 = 3,
+  FM_GREEN_HEJ6 = 4,
+  FM_GREEN_HEJ8 = 5,
+  FM_GREEN_HEJ10 = 6,
+  FM_GREEN_HEJ0 = 7
+} fm_green;
 
 /* Arithmetic of the transforms.  FM_F32 plans take their twiddles and Green's
  * spectrum from FP64 evaluations rounded once to FP32. */

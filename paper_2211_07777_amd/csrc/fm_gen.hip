@@ -93,8 +93,104 @@ __device__ double bessel_k(int nu, double x) {
 
 
 
+// Si(x) = int_0^x sin(t) / t dt for x >= 0.  Below 4 the Taylor series
+// sum_n (-1)^n x^(2n+1) / ((2n+1) (2n+1)!) (terms stay below 2, so no digits are lost to
+// cancellation); from 4 on Si(x) = pi/2 + Im E1(i x), with E1(z) = e^{-z} / (z + 1 -
+// 1/(z + 3 - 4/(z + 5 - ...))) evaluated by the modified Lentz method (the continued
+// fraction converges quickly for |z| >= 4).
+__device__ double sine_integral(double x) {
+  const double pi = 3.14159265358979323846;
+  if (x < 4.0) {
+    const double x2 = x * x;
+    double term = x, sum = x;  // term = (-1)^n x^(2n+1) / (2n+1)!
+    for (int n = 1; n < 40; ++n) {
+      term *= -x2 / ((2.0 * n) * (2.0 * n + 1.0));
+      const double add = term / (2.0 * n + 1.0);
+      sum += add;
+      if (fabs(add) < 1e-18 * fabs(sum)) break;
+    }
+    return sum;
+  }
+  // continued fraction for e^{z} E1(z), z = i x: b_0 = z + 1, a_j = -j^2, b_j = z + 2j + 1
+  const double tiny = 1e-300;
+  double br = 1.0, bi = x;          // b_0
+  double fr = br, fi = bi;          // f = b_0
+  double cr = fr, ci = fi, dr = 0.0, di = 0.0;
+  for (int j = 1; j < 100000; ++j) {
+    const double a = -(double)j * (double)j;
+    br += 2.0;                       // b_j = 2j + 1 + i x
+    // d = 1 / (b + a d)
+    double tr = br + a * dr, ti = bi + a * di;
+    if (fabs(tr) + fabs(ti) < tiny) tr = tiny;
+    double den = tr * tr + ti * ti;
+    dr = tr / den;
+    di = -ti / den;
+    // c = b + a / c
+    den = cr * cr + ci * ci;
+    cr = br + a * cr / den;
+    ci = bi - a * ci / den;
+    if (fabs(cr) + fabs(ci) < tiny) cr = tiny;
+    const double er = cr * dr - ci * di, ei = cr * di + ci * dr;  // delta = c d
+    const double nr = fr * er - fi * ei, ni = fr * ei + fi * er;
+    fr = nr;
+    fi = ni;
+    if (fabs(er - 1.0) + fabs(ei) < 1e-16) break;
+  }
+  // E1(i x) = e^{-i x} / f
+  const double den = fr * fr + fi * fi;
+  const double qr = fr / den, qi = -fi / den;  // 1 / f
+  double sn, cs;
+  sincos(x, &sn, &cs);
+  const double im = -sn * qr + cs * qi;        // Im[(cos x - i sin x)(qr + i qi)]
+  return 0.5 * pi + im;
+}
+
+// Regularised kernels (FM_GREEN_HEJ*): variant 2..6 is the order m = 2 (variant - 1),
+// variant 7 the spectral truncation.  Real space (three convolution directions), with
+// p = r / eps:
+//   G = -(1 / 4 pi r) [erf(p / sqrt 2) + sqrt(2/pi) p exp(-p^2 / 2) Q_m(p^2)],
+//   Q_2 = 0, Q_4 = 1/2, Q_6 = (7 - p^2) / 8, Q_8 = (57 - 16 p^2 + p^4) / 48,
+//   Q_10 = (561 - 233 p^2 + 29 p^4 - p^6) / 384,
+// which solves lap G = zeta_m for the Gaussian-Laguerre source; G(0) = -sqrt(2/pi) C_m /
+// (4 pi eps) with C_m = 1, 3/2, 15/8, 35/16, 315/128 (the limit of the bracket / p).
+// Truncated kernel: G = -Si(k_c r) / (2 pi^2 r), G(0) = -k_c / (2 pi^2).  Spectral form
+// (no convolution direction): -zeta_hat(k) / k^2, zero at k = 0.
+__device__ double hej_value(const GreenGen& g, double r, double k) {
+  const double pi = 3.14159265358979323846;
+  const int q = g.variant - 2;
+  if (g.du == 3) {
+    if (g.variant == 7)
+      return r > 0.0 ? -sine_integral(g.kc * r) / (2.0 * pi * pi * r) : -g.kc / (2.0 * pi * pi);
+    const double sq2pi = sqrt(2.0 / pi);
+    if (r == 0.0) {
+      const double cm[5] = {1.0, 1.5, 1.875, 2.1875, 2.4609375};
+      return -sq2pi * cm[q] / (4.0 * pi * g.eps);
+    }
+    const double p = r / g.eps, p2 = p * p;
+    double poly;
+    switch (q) {
+      case 0: poly = 0.0; break;
+      case 1: poly = 0.5; break;
+      case 2: poly = (7.0 - p2) / 8.0; break;
+      case 3: poly = (57.0 + p2 * (-16.0 + p2)) / 48.0; break;
+      default: poly = (561.0 + p2 * (-233.0 + p2 * (29.0 - p2))) / 384.0; break;
+    }
+    return -(erf(p / sqrt(2.0)) + sq2pi * p * exp(-0.5 * p2) * poly) / (4.0 * pi * r);
+  }
+  if (k == 0.0) return 0.0;
+  if (g.variant == 7) return k <= g.kc * (1.0 + 1e-12) ? -1.0 / (k * k) : 0.0;
+  const double s = 0.5 * (k * g.eps) * (k * g.eps);
+  double term = 1.0, sum = 1.0;  // sum_{j <= q} s^j / j!
+  for (int j = 1; j <= q; ++j) {
+    term *= s / j;
+    sum += term;
+  }
+  return -exp(-s) * sum / (k * k);
+}
+
 __device__ double green_value(const GreenGen& g, double rho, double k) {
   const double pi = 3.14159265358979323846;
+  if (g.variant >= 2) return hej_value(g, rho, k);
   if (g.du == 3) {
     if (rho > 0.0) return -1.0 / (4.0 * pi * rho);
     const double s = -3.0 / (8.0 * pi * g.r_eq);

@@ -266,6 +266,7 @@ struct GreenGen {
   double h[3];               // spacing (convolution directions)
   double dw[3], shift[3];    // spectral: omega = dw * (index + shift)
   int32_t n[3];              // sample extents
+  double eps, kc;            // regularised kernels: smoothing length, spectral cut-off
 };
 
 }  // namespace fm

@@ -612,6 +612,11 @@ int make_tables_and_green(fm_plan_s* p, hipStream_t st, bool deferred) {
   g.cellvol = vol;
   if (du == 3) g.r_eq = std::cbrt(3.0 * vol / (4.0 * M_PI));
   if (du == 2) g.r_eq = std::sqrt(vol / M_PI);
+  if (p->green >= FM_GREEN_HEJ2) {
+    const double hc = std::cbrt(p->h[0] * p->h[1] * p->h[2]);
+    g.eps = 2.0 * hc;
+    g.kc = M_PI / hc;
+  }
   const int64_t ns = (int64_t)Fs[0] * Fs[1] * Fs[2];
   double* S = nullptr;
   if (hipMalloc(&S, sizeof(double) * ns) != hipSuccess) return FM_E_NOMEM;
@@ -859,6 +864,10 @@ int build_plan(fm_plan_s* p) {
   for (int a = 0; a < 3; ++a) {
     const int rc = plan_axis(p->n[a], p->h[a], node, p->bc[a][0], p->bc[a][1], &p->ax[a]);
     if (rc) return rc;
+  }
+  if (p->green >= FM_GREEN_HEJ2) {  // regularised kernels: all directions unbounded or none
+    const int nu = (int)p->ax[0].unb + (int)p->ax[1].unb + (int)p->ax[2].unb;
+    if (nu != 0 && nu != 3) return FM_E_KIND;
   }
   if (p->kind != FM_POISSON) {
     if (p->ncomp != 3) return FM_E_KIND;
@@ -1363,7 +1372,7 @@ namespace {
 
 int check_enums(int layout, int green, int prec, int kind, int ncomp) {
   if (layout != FM_CELL && layout != FM_NODE) return FM_E_KIND;
-  if (green != FM_GREEN_CHAT2 && green != FM_GREEN_CHAT2_VOL) return FM_E_KIND;
+  if (green < FM_GREEN_CHAT2 || green > FM_GREEN_HEJ0) return FM_E_KIND;
   if (prec != FM_F64 && prec != FM_F32) return FM_E_KIND;
   if (kind < FM_POISSON || kind > FM_BIOT_SAVART_FD6) return FM_E_KIND;
   if (ncomp < 1 || ncomp > 64) return FM_E_KIND;

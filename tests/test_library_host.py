@@ -66,6 +66,20 @@ def test_rejects_bad_arguments():
     assert e.value.status == -4
 
 
+def test_regularised_kernels_need_three_or_no_unbounded_directions():
+    for g in (F.HEJ2, F.HEJ4, F.HEJ6, F.HEJ8, F.HEJ10, F.HEJ0):
+        F.plan_inspect([8, 8, 8], [0.1] * 3, [[3, 3]] * 3, 0, g)
+        F.plan_inspect([8, 8, 8], [0.1] * 3, [[0, 3], [3, 1], [3, 3]], 1, g)
+        F.plan_inspect([8, 8, 8], [0.1] * 3, [[2, 2], [0, 1], [1, 1]], 0, g)
+        for bc in ([[3, 3], [2, 2], [2, 2]], [[3, 3], [3, 3], [0, 0]]):
+            with pytest.raises(F.FluxmiError) as e:
+                F.plan_inspect([8, 8, 8], [0.1] * 3, bc, 0, g)
+            assert e.value.status == -4
+    with pytest.raises(F.FluxmiError) as e:
+        F.plan_inspect([8, 8, 8], [0.1] * 3, [[3, 3]] * 3, 0, 8)
+    assert e.value.status == -4
+
+
 def test_workspace_and_padding_sizes():
     # fully unbounded 512^3 cell, FP32, 3 components: two spectral buffers per component
     info = F.plan_inspect([512] * 3, [2 / 512] * 3, [[3, 3]] * 3, 0, F.CHAT2, F.F32, F.BIOT_SAVART, 3)
