@@ -702,6 +702,43 @@ __device__ __forceinline__ void store_real(const PassDesc& d, void* out, const T
                   d.out_n, d.mag_out, d.B, d.mag_B, ti.b0, ti.c, d.fix, val);
 }
 
+// The FFT lines of a plain tile, in natural order in LDS (line f at buf + f ls), written
+// into the output layout by the pass's scatter.
+template <typename T, int MC, int KIND, class P>
+__device__ __forceinline__ void plain_store(const PassDesc& d, void* out, const TileIdx& ti,
+                                            const cpx<T>* buf, P tw) {
+  const int scatter = KIND == K_ANY ? d.scatter : scatter_of(KIND);
+  const int nl = ti.nl;
+  const int M = MC > 1 ? MC : d.M;
+  const int ls = fft_line_stride(M);
+  const int64_t out_off = ti.comp * d.out_s_comp + ti.c * d.out_s_c + ti.b0 * d.out_s_b;
+  if (scatter == S_CPLX) {
+    auto val = [&](int l, int j) { return buf[l * ls + pad16(j < M ? j : j - M)]; };
+    store_tile<false>(reinterpret_cast<cpx<T>*>(out) + out_off, d.out_s_line, d.out_s_b, d.out_s_c,
+                      nl, d.out_n, d.mag_out, d.B, d.mag_B, ti.b0, ti.c, d.fix, val);
+  } else if (scatter == S_R2C2) {
+    auto val = [&](int l, int k) {
+      const cpx<T>* z = buf + (l >> 1) * ls;
+      const cpx<T> zk = z[pad16(k)], zm = z[pad16(k == 0 ? 0 : M - k)];
+      if (l & 1) return cpx<T>{T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x)};
+      return cpx<T>{T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
+    };
+    store_tile<false>(reinterpret_cast<cpx<T>*>(out) + out_off, d.out_s_line, d.out_s_b, d.out_s_c,
+                      nl, d.out_n, d.mag_out, d.B, d.mag_B, ti.b0, ti.c, d.fix, val);
+  } else if (scatter == S_REAL2) {
+    auto val = [&](int l, int j) {
+      const cpx<T> z = buf[(l >> 1) * ls + pad16(j < M ? j : j - M)];
+      return (l & 1) ? z.y : z.x;
+    };
+    if (d.has_fix) store_real<T, MC, true>(d, out, ti, out_off, val);
+    else store_real<T, MC, false>(d, out, ti, out_off, val);
+  } else {
+    auto val = [&](int l, int j) { return scatter_r2r<T>(buf, ls, d.r2r, tw, l, j); };
+    if (d.has_fix) store_real<T, MC, true>(d, out, ti, out_off, val);
+    else store_real<T, MC, false>(d, out, ti, out_off, val);
+  }
+}
+
 // DIRECT: forward complex or real-to-complex lines read by the first FFT stage straight
 // from contiguous input lines at gin (the tile's first line) instead of the LDS raw tile.
 template <typename T, int MC, int KIND, bool DIRECT = false, class P>
@@ -783,31 +820,7 @@ __device__ void plain_compute(const PassDesc& d, void* out, const TileIdx& ti, c
   }
 
   // 3) write the lines into the output layout
-  if (scatter == S_CPLX) {
-    auto val = [&](int l, int j) { return buf[l * ls + pad16(j < M ? j : j - M)]; };
-    store_tile<false>(reinterpret_cast<cpx<T>*>(out) + out_off, d.out_s_line, d.out_s_b, d.out_s_c,
-                      nl, d.out_n, d.mag_out, d.B, d.mag_B, ti.b0, ti.c, d.fix, val);
-  } else if (scatter == S_R2C2) {
-    auto val = [&](int l, int k) {
-      const cpx<T>* z = buf + (l >> 1) * ls;
-      const cpx<T> zk = z[pad16(k)], zm = z[pad16(k == 0 ? 0 : M - k)];
-      if (l & 1) return cpx<T>{T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x)};
-      return cpx<T>{T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
-    };
-    store_tile<false>(reinterpret_cast<cpx<T>*>(out) + out_off, d.out_s_line, d.out_s_b, d.out_s_c,
-                      nl, d.out_n, d.mag_out, d.B, d.mag_B, ti.b0, ti.c, d.fix, val);
-  } else if (scatter == S_REAL2) {
-    auto val = [&](int l, int j) {
-      const cpx<T> z = buf[(l >> 1) * ls + pad16(j < M ? j : j - M)];
-      return (l & 1) ? z.y : z.x;
-    };
-    if (d.has_fix) store_real<T, MC, true>(d, out, ti, out_off, val);
-    else store_real<T, MC, false>(d, out, ti, out_off, val);
-  } else {
-    auto val = [&](int l, int j) { return scatter_r2r<T>(buf, ls, d.r2r, tw, l, j); };
-    if (d.has_fix) store_real<T, MC, true>(d, out, ti, out_off, val);
-    else store_real<T, MC, false>(d, out, ti, out_off, val);
-  }
+  plain_store<T, MC, KIND>(d, out, ti, buf, tw);
 }
 
 // ---------------------------------------------------------------------------------

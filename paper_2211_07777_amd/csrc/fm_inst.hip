@@ -48,18 +48,42 @@ static hipError_t launch_wave_e(const PassDesc& d, const PassDesc* dev, const vo
   }
 }
 
+// Plain passes in the per-wavefront kernel: four wavefronts per workgroup, one workgroup
+// per tile.
+template <int KIND, int E>
+static hipError_t launch_wave_plain_e(const PassDesc& d, const PassDesc* dev, const void* in,
+                                      void* out, hipStream_t st) {
+  if constexpr (wave_length(FM_MC, E) && KIND >= K_C2C_F && KIND <= K_R2R) {
+    if (d.lds_bytes > kSoftLds) {
+      const hipError_t e = allow_full_lds<&wave_plain_kernel<FM_T, FM_MC, KIND, E>>();
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((wave_plain_kernel<FM_T, FM_MC, KIND, E>), dim3(d.tiles), dim3(kThreads),
+                       d.lds_bytes, st, dev, in, out);
+    return hipGetLastError();
+  } else {
+    (void)d; (void)dev; (void)in; (void)out; (void)st;
+    return hipErrorInvalidValue;
+  }
+}
+
 template <int KIND>
 static hipError_t launch_wave(const PassDesc& d, const PassDesc* dev, const void* in, void* out,
                               hipStream_t st) {
-  if (d.wave == 16) return launch_wave_e<KIND, 16>(d, dev, in, out, st);
-  if (d.wave == 8) return launch_wave_e<KIND, 8>(d, dev, in, out, st);
+  if constexpr (fused_of(KIND)) {
+    if (d.wave == 16) return launch_wave_e<KIND, 16>(d, dev, in, out, st);
+    if (d.wave == 8) return launch_wave_e<KIND, 8>(d, dev, in, out, st);
+  } else {
+    if (d.wave == 16) return launch_wave_plain_e<KIND, 16>(d, dev, in, out, st);
+    if (d.wave == 8) return launch_wave_plain_e<KIND, 8>(d, dev, in, out, st);
+  }
   return hipErrorInvalidValue;
 }
 
 template <int KIND>
 static hipError_t launch_kind(const PassDesc& d, const PassDesc* dev, const void* in, void* out,
                               hipStream_t st) {
-  if constexpr (KIND == K_F_C2C || KIND == K_F_CURL) {
+  if constexpr (KIND == K_F_C2C || KIND == K_F_CURL || (KIND >= K_C2C_F && KIND <= K_R2R)) {
     if (d.wave) return launch_wave<KIND>(d, dev, in, out, st);
   }
   static const bool persistent = [] {

@@ -251,9 +251,12 @@ struct PassDesc {
   int32_t lds_tabs;         // compile-time-length kernels that allow it: 1 = twiddle tables
                             // staged in LDS (persistent loop, or one tile per workgroup);
                             // 0 = one tile per workgroup reading them from global memory
-  int32_t wave;             // fused complex pass in the per-wavefront kernel (fm_wave.h):
-                            // its values per lane E (16 or 8; 0: not that kernel); B =
-                            // lines per workgroup, a multiple of wave_lines(M, E)
+  int32_t wave;             // pass in a per-wavefront kernel (fm_wave.h): its values per
+                            // lane E (16 or 8; 0: not that kernel).  Fused complex passes:
+                            // B = lines per workgroup, a multiple of wave_lines(M, E).
+                            // Plain passes: four wavefronts, B = 4 wave_lines(M, E) FFT
+                            // lines (times 2 real lines per FFT for the packed kinds)
+  int32_t wave_rs;          // plain passes: raw tile line stride, in input elements
   const void* wtw;          // its stage twiddle tables: E = 16 (wave_tw_size(M, 16) entries)
   const void* wtw8;         // and E = 8
 };

@@ -258,7 +258,7 @@ struct fm_plan_s {
   std::map<int, void*> tw;
   std::map<int, void*> stw;
   std::map<int, void*> tw64;
-  std::map<int, void*> wtw;  // stage twiddles of the per-wavefront kernels
+  std::map<int, void*> wtw;  // stage twiddles of the per-wavefront kernels, by (M << 5) | E
   void* dtab = nullptr;      // central-difference symbols of the curl (line, b, c tables)
   void* ws_internal = nullptr;
   std::mutex ws_mu;  // guards the lazy allocation of ws_internal
@@ -392,13 +392,36 @@ int choose_tile(fm::PassDesc* d, size_t elem, int comps, bool fused_r2r, int nb,
 // passes of a power-of-two length whose lines are contiguous in memory (every fused
 // complex pass: the last axis is the fastest of its layout); three-component lines of 16
 // values per lane in FP32 only.
+int wave_plain_rs(const fm::PassDesc& d, int E);
+
 bool wave_capable(const fm::PassDesc& d, size_t elem, int E) {
   // the kernels are compiled with the compile-time-length classes (fm_inst.hip)
-  if (!d.fused || d.gather != fm::G_CPLX || d.long_rt || !fm::wave_length(d.M, E) || !fm::is_fast_len(d.M))
-    return false;
+  if (d.long_rt || !fm::wave_length(d.M, E) || !fm::is_fast_len(d.M)) return false;
+  if (!d.fused) return wave_plain_rs(d, E) > 0;
+  if (d.gather != fm::G_CPLX) return false;
   if (d.g.curl && elem != 4 && E == 16) return false;
   return d.in_s_line == 1 && d.out_s_line == 1;
 }
+
+// The per-wavefront plain kernel (fm_wave.h, wave_plain_tile): any unfused pass of a
+// power-of-two length.  Its tile is four wavefronts of L = wave_lines(M, E) FFT lines,
+// pk tile lines per FFT line (2 for the packed real kinds).  The raw lines of a
+// wavefront share the LDS region of its FFT lines (L line strides of complex values):
+// returns their stride in input elements (odd when there is room, against LDS bank
+// conflicts between consecutive lines), or 0 when the lines do not fit.
+int wave_plain_pk(const fm::PassDesc& d) { return d.gather == fm::G_CPLX ? 1 : 2; }
+
+int wave_plain_rs(const fm::PassDesc& d, int E) {
+  if (d.fused || !fm::wave_length(d.M, E) || d.in_n < 1) return 0;
+  const int pk = wave_plain_pk(d);
+  const int cap = fm::fft_line_stride(d.M) * (d.in_cplx ? 1 : 2) / pk;  // per raw line
+  const int rs = d.in_n | 1;
+  if (rs <= cap) return rs;
+  return d.in_n <= cap ? d.in_n : 0;
+}
+
+// Input values per thread of the plain per-wavefront kernel's register stage.
+int wave_plain_u(const fm::PassDesc& d, int E) { return d.gather == fm::G_REAL2 ? 2 * E : E + 1; }
 
 bool wave_capable(const fm::PassDesc& d, size_t elem) {
   return wave_capable(d, elem, 16) || wave_capable(d, elem, 8);
@@ -423,10 +446,15 @@ size_t wave_lds(int B, int M, size_t elem) {
 // position (ncomp, or 1 for the three-component curl).
 bool set_wave(fm::PassDesc* d, size_t elem, int W, int comp_tiles, int E) {
   if (!wave_capable(*d, elem, E) || (W != 1 && W != 2 && W != 4)) return false;
-  const int B = W * fm::wave_lines(d->M, E);
-  const size_t lds = wave_lds(B, d->M, elem);
+  // plain passes: four wavefronts (the tile's loads and stores use every thread)
+  if (!d->fused && W != 4) return false;
+  const int F = W * fm::wave_lines(d->M, E);  // FFT lines per workgroup
+  const int B = d->fused ? F : F * wave_plain_pk(*d);
+  const size_t lds = wave_lds(F, d->M, elem);
   if (lds > (size_t)fm::kMaxLds) return false;
+  if (!d->fused && (int64_t)B * d->in_n > (int64_t)fm::kThreads * wave_plain_u(*d, E)) return false;
   d->wave = E;
+  d->wave_rs = d->fused ? 0 : wave_plain_rs(*d, E);
   d->B = B;
   d->lds_bytes = (int)lds;
   d->raw_off = d->g_off = d->tab_off = 0;
@@ -529,18 +557,23 @@ int make_tables_and_green(fm_plan_s* p, hipStream_t st, bool deferred) {
     p->pass[i].stw = p->stw[M];
   }
 
-  // stage twiddles of the per-wavefront kernel (the fused pass may run there, now or
-  // after tuning)
-  for (const int E : {16, 8}) {
-    if (!wave_capable(p->pass[2], p->elem, E)) continue;
-    const int M = p->pass[2].M;
-    void* ptr = nullptr;
-    const size_t n = (size_t)std::max(1, fm::wave_tw_size(M, E));
-    if (hipMalloc(&ptr, sizeof(T) * 2 * n) != hipSuccess) return FM_E_NOMEM;
-    p->wtw[E] = ptr;
-    p->table_bytes += sizeof(T) * 2 * n;
-    FM_HIP(fm::launch_wave_twiddles<T>(ptr, M, E, st));
-    (E == 16 ? p->pass[2].wtw : p->pass[2].wtw8) = ptr;
+  // stage twiddles of the per-wavefront kernels (a pass may run there, now or after
+  // tuning), one table per length and values per lane
+  for (int i = 0; i < 5; ++i) {
+    for (const int E : {16, 8}) {
+      if (!wave_capable(p->pass[i], p->elem, E)) continue;
+      const int M = p->pass[i].M;
+      const int key = (M << 5) | E;
+      if (!p->wtw.count(key)) {
+        void* ptr = nullptr;
+        const size_t n = (size_t)std::max(1, fm::wave_tw_size(M, E));
+        if (hipMalloc(&ptr, sizeof(T) * 2 * n) != hipSuccess) return FM_E_NOMEM;
+        p->wtw[key] = ptr;
+        p->table_bytes += sizeof(T) * 2 * n;
+        FM_HIP(fm::launch_wave_twiddles<T>(ptr, M, E, st));
+      }
+      (E == 16 ? p->pass[i].wtw : p->pass[i].wtw8) = p->wtw[key];
+    }
   }
 
   // the curl's derivative factor of every DFT mode k (signed k_s) of the three directions
@@ -785,7 +818,7 @@ bool wave_in_bounds(const fm::PassDesc& d, int64_t in_size, int64_t out_size, si
 // Host-side check of one pass against the buffers and the LDS / register budgets; the
 // index ranges mirror what the tile kernels touch.
 bool pass_in_bounds(const fm::PassDesc& d, int64_t in_size, int64_t out_size, size_t elem) {
-  if (d.wave) return wave_in_bounds(d, in_size, out_size, elem);
+  if (d.wave && d.fused) return wave_in_bounds(d, in_size, out_size, elem);
   auto span = [](int nc, int64_t sc, int nb, int64_t sb, int n, int64_t sl) {
     return (int64_t)(nc - 1) * sc + (int64_t)(nb - 1) * sb + (int64_t)(n - 1) * sl;
   };
@@ -825,6 +858,23 @@ bool pass_in_bounds(const fm::PassDesc& d, int64_t in_size, int64_t out_size, si
   const int comps = (d.fused && d.g.curl) ? 3 : 1;
   const int packs = (d.gather == fm::G_CPLX) ? 1 : 2;
   const int F = comps * ((d.B + packs - 1) / packs);
+  if (d.wave) {
+    // plain pass in the per-wavefront kernel: four wavefronts of wave_lines FFT lines, the
+    // raw lines of each inside its LDS region, the register stage holds the tile
+    const int E = d.wave;
+    if (d.fused || !wave_capable(d, elem, E) || d.wave_rs != wave_plain_rs(d, E)) return false;
+    const int L = fm::wave_lines(M, E);
+    if (d.B != 4 * L * packs || (int64_t)d.B * d.in_n > (int64_t)fm::kThreads * wave_plain_u(d, E))
+      return false;
+    if (d.wave_rs < d.in_n || (int64_t)L * packs * d.wave_rs >
+                                  (int64_t)L * fm::fft_line_stride(M) * (d.in_cplx ? 1 : 2))
+      return false;
+    if ((size_t)d.lds_bytes < wave_lds(4 * L, M, elem) || d.lds_bytes > fm::kMaxLds) return false;
+    if (d.raw_off != 0 || d.stw_n + d.tw_n != 0) return false;
+    if (tile_in_span_bytes(d, elem) >= (int64_t(1) << 32)) return false;
+    const int nbt = (d.nb + d.B - 1) / d.B;
+    return d.tiles == nbt * d.nc * d.ncomp;
+  }
   const int cls = pass_class(d);
   if (d.long_rt && elem != 8) return false;
   if ((int64_t)F * M > (int64_t)fm::kThreads * fm::elems_per_thread((int)elem, cls)) return false;
@@ -1644,8 +1694,9 @@ int launch_mode(const fm::PassDesc& d, size_t elem) {
 
 // A pass re-tiled with at most bmax lines per tile, in launch mode `mode` (1 persistent
 // with LDS tables, 0 one tile per workgroup with LDS tables, 2 one tile per workgroup
-// with global tables); false if no such tiling is valid for this plan (the
-// compile-time-length kernels address a tile with 32-bit offsets).
+// with global tables, 3 / 4 the per-wavefront kernels with 16 / 8 values per lane);
+// false if no such tiling is valid for this plan (the compile-time-length kernels
+// address a tile with 32-bit offsets).
 bool retile(const fm_plan_s* p, int i, int bmax, int mode, fm::PassDesc* out) {
   fm::PassDesc d = p->pass[i];
   const bool fused_curl = (i == 2) && p->kind != FM_POISSON;
@@ -1659,8 +1710,8 @@ bool retile(const fm_plan_s* p, int i, int bmax, int mode, fm::PassDesc* out) {
     if (!wave_capable(d, p->elem, E)) return false;
     for (const int W : {4, 2, 1}) {
       fm::PassDesc w = d;
-      if (W * fm::wave_lines(d.M, E) > bmax || !set_wave(&w, p->elem, W, fused_curl ? 1 : p->ncomp, E))
-        continue;
+      const int lines = W * fm::wave_lines(d.M, E) * (d.fused ? 1 : wave_plain_pk(d));
+      if (lines > bmax || !set_wave(&w, p->elem, W, fused_curl ? 1 : p->ncomp, E)) continue;
       if (!pass_in_bounds(w, sizes_in[i], sizes_out[i], p->elem)) return false;
       *out = w;
       return true;

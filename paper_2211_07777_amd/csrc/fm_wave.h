@@ -201,4 +201,109 @@ void wave_pass_kernel(const PassDesc* __restrict__ dp, const void* in, void* out
   }
 }
 
+// ---------------------------------------------------------------------------------
+// Per-wavefront form of the plain passes (one axis, forward or inverse, any gather and
+// scatter).  The tile is staged in LDS as in the LDS-tile kernel, so strided lines are
+// still loaded and stored in coalesced rows, but each wavefront then transforms its own
+// FFT lines in registers with the schedule above: two workgroup barriers per tile
+// instead of one per radix stage.  Four wavefronts of L = 64 / P FFT lines each; a
+// packed kind (two real lines per FFT) holds 2 L tile lines per wavefront.  The raw
+// lines of wavefront w sit inside the LDS region of its own FFT lines: all its raw
+// values are read before its first exchange write, and no other wavefront touches the
+// region until the next workgroup barrier.
+// ---------------------------------------------------------------------------------
+template <typename T, int M, int KIND, int E_>
+struct WavePlain {
+  static constexpr int E = E_;
+  static constexpr int P = M / E;                         // lanes per FFT line
+  static constexpr int L = 64 / P;                        // FFT lines per wavefront
+  static constexpr int PK = gather_of(KIND) == G_CPLX ? 1 : 2;  // tile lines per FFT line
+  static constexpr int RW = L * PK;                       // tile lines per wavefront
+  static constexpr int LS = fft_line_stride(M);
+  static constexpr bool CIN = in_cplx_of(KIND);
+  using In = typename std::conditional<CIN, cpx<T>, T>::type;
+  static constexpr int REGION = L * LS * (CIN ? 1 : 2);   // a wavefront's LDS, in In units
+  static constexpr int U = KIND == K_R2C ? 2 * E : E + 1; // input values per thread
+};
+
+// Registers -> raw tile: tile line l at (l / RW) REGION + (l mod RW) rs.
+template <class WP, class Stage>
+__device__ __forceinline__ void commit_wave(const Stage& v, const PassDesc& d, const TileIdx& ti,
+                                            char* smem) {
+  using In = typename WP::In;
+  const TileWalk w = in_walk(d, ti);
+  In* raw = reinterpret_cast<In*>(smem);
+  const int rs = d.wave_rs;
+#pragma unroll
+  for (int u = 0; u < WP::U; ++u) {
+    int l, i;
+    if (w.at((int)threadIdx.x + u * kThreads, l, i))
+      raw[(l / WP::RW) * WP::REGION + (l % WP::RW) * rs + i] = v.get(u);
+  }
+}
+
+template <typename T, int M, int KIND, int E>
+__device__ __forceinline__ void wave_plain_tile(const PassDesc& d, const void* in, void* out,
+                                                char* smem, int tile) {
+  using WP = WavePlain<T, M, KIND, E>;
+  using In = typename WP::In;
+  constexpr int P = WP::P, L = WP::L, PK = WP::PK;
+  constexpr int S = (KIND == K_C2C_I || KIND == K_C2R) ? +1 : -1;
+  const TileIdx ti = tile_index(d, tile);
+  {
+    RegStage<T, In, WP::U> st;
+    fetch<WP::U, 1, false, In>(st, d, in, ti);
+    commit_wave<WP>(st, d, ti, smem);
+  }
+  __syncthreads();
+  const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+  const int j = lane % P, lf = lane / P;  // lane of the line, line of the wavefront
+  const int f = wave * L + lf;            // FFT line of the tile
+  cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem);
+  const GTab<T> tw4 = gptr<cpx<T>>(d.tw);
+  if (f < (ti.nl + PK - 1) / PK) {
+    const In* raw = reinterpret_cast<const In*>(smem) + wave * WP::REGION;
+    const int nlw = ti.nl - wave * WP::RW;  // tile lines from the wavefront's first
+    const int rs = d.wave_rs;
+    cpx<T> v[E];
+    if constexpr (gather_of(KIND) == G_CPLX) {
+      const GatherCplx<T> g{raw, rs, d.n_data};
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = g(lf, j + P * m);
+    } else if constexpr (gather_of(KIND) == G_REAL2) {
+      const GatherReal2<T> g{raw, rs, d.n_data, nlw};
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = g(lf, j + P * m);
+    } else if constexpr (gather_of(KIND) == G_HERM2) {
+      const GatherHerm2<T> g{raw, rs, M, nlw};
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = g(lf, j + P * m);
+    } else {
+      const GatherR2R<T, GTab<T>> g{raw, rs, d.in_n, nlw, d.r2r, tw4};
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = g(lf, j + P * m);
+    }
+    cpx<T>* line = buf + (size_t)f * WP::LS;
+    wave_stages<T, M, E, 0, S>(v, j, line, gptr<cpx<T>>(E == 16 ? d.wtw : d.wtw8));
+    wave_lds_sync();  // the last exchange's reads are done
+#pragma unroll
+    for (int m = 0; m < E; ++m) line[pad16(j + P * m)] = v[m];
+  }
+  __syncthreads();
+  plain_store<T, M, KIND>(d, out, ti, buf, tw4);
+}
+
+template <typename T, int M, int KIND, int E>
+__global__ __launch_bounds__(kThreads) void wave_plain_kernel(const PassDesc* __restrict__ dp,
+                                                              const void* in, void* out) {
+  extern __shared__ __align__(16) char smem[];
+  const PassDesc& d = *dp;
+  for (int k = 0;; ++k) {
+    const int tile = xcd_tile(blockIdx.x, gridDim.x, k, d.tiles);
+    if (tile < 0) return;
+    if (k > 0) __syncthreads();  // the previous tile's LDS reads are finished
+    wave_plain_tile<T, M, KIND, E>(d, in, out, smem, tile);
+  }
+}
+
 }  // namespace fm
