@@ -515,9 +515,9 @@ struct GatherR2R {  // symmetric extension of two real lines, with pre-twiddle
   P tw;  // 4M table
   // Branch-free: the mirrored source index and its weight are selected per lane, the
   // index is clamped into the line, and a sample outside the data gets weight 0.
-  __device__ cpx<T> operator()(int f, int m) const {
+  // slot m of the extension: its source index jc in the line and its real weight c
+  __device__ __forceinline__ void source(int m, int& jc, T& c) const {
     const int nh = r.nh, M = 2 * nh;
-    const int l = 2 * f;
     const T eps = r.b2 ? T(-1) : T(1);          // wrap factor of a full period
     const T sigma = r.sin ? -eps : eps;          // sign of the mirrored sample
     int p;
@@ -535,9 +535,23 @@ struct GatherR2R {  // symmetric extension of two real lines, with pre-twiddle
     }
     const int j = r.in_rev ? r.in_base - p : p - r.in_base;
     const bool ok = p >= r.plo && p <= r.phi && j >= 0 && j < in_n;
-    const int jc = ok ? j : 0;
+    jc = ok ? j : 0;
     const T w = T(p == r.plo ? r.wlo : (p == r.phi ? r.whi : 2));
-    const T c = ok ? coef * w * T(0.5) : T(0);
+    c = ok ? coef * w * T(0.5) : T(0);
+  }
+  // the complex weight of slot m (c times the pre-twiddle)
+  __device__ __forceinline__ cpx<T> weight(int m, int& jc) const {
+    T c;
+    source(m, jc, c);
+    cpx<T> z = {c, T(0)};
+    if (r.b2) z = cmul(z, twid<T>(tw, 2 * m));
+    return z;
+  }
+  __device__ cpx<T> operator()(int f, int m) const {
+    const int l = 2 * f;
+    int jc;
+    T c;
+    source(m, jc, c);
     const bool two = l + 1 < nl;
     const T a = raw[l * rs + jc];
     const T b = raw[(two ? l + 1 : l) * rs + jc];

@@ -48,18 +48,31 @@ static hipError_t launch_wave_e(const PassDesc& d, const PassDesc* dev, const vo
   }
 }
 
-// Plain passes in the per-wavefront kernel: four wavefronts per workgroup, one workgroup
-// per tile.
+// Plain passes in the per-wavefront kernel: four wavefronts per workgroup, a persistent
+// grid of as many workgroups as can be resident at once (each loops over its tiles).
 template <int KIND, int E>
 static hipError_t launch_wave_plain_e(const PassDesc& d, const PassDesc* dev, const void* in,
                                       void* out, hipStream_t st) {
   if constexpr (wave_length(FM_MC, E) && KIND >= K_C2C_F && KIND <= K_R2R) {
+    constexpr auto kern = &wave_plain_kernel<FM_T, FM_MC, KIND, E>;
     if (d.lds_bytes > kSoftLds) {
-      const hipError_t e = allow_full_lds<&wave_plain_kernel<FM_T, FM_MC, KIND, E>>();
+      const hipError_t e = allow_full_lds<kern>();
       if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((wave_plain_kernel<FM_T, FM_MC, KIND, E>), dim3(d.tiles), dim3(kThreads),
-                       d.lds_bytes, st, dev, in, out);
+    static int resident[kMaxLds / 256 + 1] = {0};
+    const int slot = d.lds_bytes / 256;
+    if (resident[slot] == 0) {
+      int per_cu = 0, dev_id = 0, cus = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kThreads, d.lds_bytes) != hipSuccess ||
+          per_cu < 1)
+        per_cu = 1;
+      if (hipGetDevice(&dev_id) != hipSuccess ||
+          hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id) != hipSuccess || cus < 1)
+        cus = 256;
+      resident[slot] = per_cu * cus;
+    }
+    const int grid = d.tiles < resident[slot] ? d.tiles : resident[slot];
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), d.lds_bytes, st, dev, in, out);
     return hipGetLastError();
   } else {
     (void)d; (void)dev; (void)in; (void)out; (void)st;

@@ -420,8 +420,17 @@ int wave_plain_rs(const fm::PassDesc& d, int E) {
   return d.in_n <= cap ? d.in_n : 0;
 }
 
+// LDS tables of the plain per-wavefront kernel after its FFT lines: stage twiddles; for
+// real-to-real passes the post-twiddles (2M entries of the 4M table) and M gather slots
+// (weight and source index, R2RSlot).
+size_t wave_plain_tab_bytes(const fm::PassDesc& d, int E, size_t elem) {
+  const bool r2r = d.gather == fm::G_R2R;
+  return (size_t)(fm::wave_tw_size(d.M, E) + (r2r ? 2 * d.M : 0)) * 2 * elem +
+         (r2r ? (size_t)d.M * (2 * elem + 8) : 0);
+}
+
 // Input values per thread of the plain per-wavefront kernel's register stage.
-int wave_plain_u(const fm::PassDesc& d, int E) { return d.gather == fm::G_REAL2 ? 2 * E : E + 1; }
+int wave_plain_u(const fm::PassDesc& d, int E) { return d.gather == fm::G_REAL2 ? 2 * E + 1 : E + 1; }
 
 bool wave_capable(const fm::PassDesc& d, size_t elem) {
   return wave_capable(d, elem, 16) || wave_capable(d, elem, 8);
@@ -453,11 +462,19 @@ bool set_wave(fm::PassDesc* d, size_t elem, int W, int comp_tiles, int E) {
   const size_t lds = wave_lds(F, d->M, elem);
   if (lds > (size_t)fm::kMaxLds) return false;
   if (!d->fused && (int64_t)B * d->in_n > (int64_t)fm::kThreads * wave_plain_u(*d, E)) return false;
+  size_t total = lds;
+  if (!d->fused) {
+    // the plain kernel's tables follow the FFT lines: stage twiddles, then the
+    // real-to-real post-twiddles (2M entries of the 4M table)
+    total = round256(lds + wave_plain_tab_bytes(*d, E, elem));
+    if (total > (size_t)fm::kMaxLds) return false;
+  }
   d->wave = E;
   d->wave_rs = d->fused ? 0 : wave_plain_rs(*d, E);
   d->B = B;
-  d->lds_bytes = (int)lds;
+  d->lds_bytes = (int)total;
   d->raw_off = d->g_off = d->tab_off = 0;
+  if (!d->fused) d->tab_off = (int)lds;
   d->stw_n = d->tw_n = 0;
   d->persist = 0;
   d->lds_tabs = 0;
@@ -869,9 +886,15 @@ bool pass_in_bounds(const fm::PassDesc& d, int64_t in_size, int64_t out_size, si
     if (d.wave_rs < d.in_n || (int64_t)L * packs * d.wave_rs >
                                   (int64_t)L * fm::fft_line_stride(M) * (d.in_cplx ? 1 : 2))
       return false;
-    if ((size_t)d.lds_bytes < wave_lds(4 * L, M, elem) || d.lds_bytes > fm::kMaxLds) return false;
+    const size_t tabs = wave_plain_tab_bytes(d, E, elem);
+    if ((size_t)d.tab_off < wave_lds(4 * L, M, elem) || d.tab_off % 16 ||
+        (size_t)d.tab_off + tabs > (size_t)d.lds_bytes || d.lds_bytes > fm::kMaxLds)
+      return false;
     if (d.raw_off != 0 || d.stw_n + d.tw_n != 0) return false;
     if (tile_in_span_bytes(d, elem) >= (int64_t(1) << 32)) return false;
+    // the output of a tile is addressed with 32-bit element offsets
+    const int64_t out_span = (int64_t)(d.B - 1) * d.out_s_b + (int64_t)(d.out_n - 1) * d.out_s_line + 1;
+    if (out_span >= (int64_t(1) << 31)) return false;
     const int nbt = (d.nb + d.B - 1) / d.B;
     return d.tiles == nbt * d.nc * d.ncomp;
   }

@@ -23,6 +23,11 @@ CASES = [
     ([16, 8, 12], [0.1, 0.1, 0.1], [[0, 3], [3, 1], [3, 3]], F.CELL, F.POISSON),       # semi-unbounded R2R
     ([32, 16, 12], [0.1, 0.1, 0.1], [[1, 1], [0, 0], [2, 2]], F.NODE, F.POISSON),      # DST-I / DCT-I
     ([16, 32, 12], [0.1, 0.07, 0.12], [[3, 3]] * 3, F.CELL, F.BIOT_SAVART),           # three components
+    # first axis not x: strided first-axis lines
+    ([16, 32, 12], [0.1, 0.07, 0.12], [[3, 3], [1, 1], [3, 3]], F.CELL, F.POISSON),    # DST along y
+    ([24, 16, 8], [0.1, 0.1, 0.1], [[3, 3], [3, 3], [0, 3]], F.CELL, F.POISSON),       # semi-unbounded z
+    ([24, 32, 8], [0.1, 0.1, 0.1], [[3, 3], [2, 2], [3, 3]], F.NODE, F.POISSON),       # R2C / C2R along y
+    ([16, 32, 12], [0.1, 0.07, 0.12], [[3, 3], [2, 2], [2, 2]], F.CELL, F.BIOT_SAVART),  # 3 comps, y first
 ]
 
 
