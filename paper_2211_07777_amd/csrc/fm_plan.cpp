@@ -1781,7 +1781,7 @@ int fm_plan_tune(fm_plan p, void* workspace_dev, void* hip_stream) {
     if (e != hipSuccess) return e;
     e = hipStreamSynchronize(st);
     float best = 1e30f;
-    for (int r = 0; r < 4 && e == hipSuccess; ++r) {
+    for (int r = 0; r < 8 && e == hipSuccess; ++r) {
       e = hipEventRecord(e0, st);
       if (e == hipSuccess)
         e = (p->prec == FM_F64) ? fm::launch_pass<double>(d, p->dpass + i, ins[i], outs[i], st)
