@@ -12,7 +12,9 @@ spectrum (Eq. of Sec. II) or by the Green's spectrum times the spectral curl (Se
 Boundary codes: 0 even, 1 odd, 2 periodic, 3 unbounded.  Layout: 0 cell, 1 node.
 Green: 0 CHAT2 as printed in Sec. IV (sphere-mean self-term times the cell volume),
 1 the sphere-mean self-term itself, 2..6 the regularised HEJ2..HEJ10 kernels, 7 HEJ0
-(the HEJ kernels with three convolution directions or none).  Kind: 0 Poisson, 1 Biot-Savart (spectral curl),
+(the HEJ kernels with three convolution directions or none), 8 LGF2, the lattice Green's
+function of the second-order discrete Laplacian (oracle/lgf.py; three convolution
+directions or none).  Kind: 0 Poisson, 1 Biot-Savart (spectral curl),
 2 / 3 / 4 Biot-Savart with the finite-difference curl of order 2 / 4 / 6.
 """
 from __future__ import annotations
@@ -69,6 +71,8 @@ def lib():
         L.oracle_transform.argtypes = [ip, dp, ip, ctypes.c_int, ctypes.c_int, dp, dp]
         L.oracle_num_threads.restype = ctypes.c_int
         L.oracle_set_num_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_lgf.argtypes = [dp, ctypes.c_long, ctypes.c_long, ctypes.c_long]
+        L.oracle_set_lgf.restype = None
         _lib = L
     return _lib
 
@@ -134,6 +138,28 @@ def user_shape(n, layout):
     return (int(n[2]) + add, int(n[1]) + add, int(n[0]) + add)
 
 
+LGF2 = 8
+_lgf_keep = {}
+
+
+def _prepare_lgf(n, h, bc, green):
+    """LGF2 with three convolution directions: tabulate the lattice Green's function at
+    offsets up to 2N along each axis and hand it to the oracle."""
+    if green != LGF2:
+        return
+    bcs = np.asarray(bc).reshape(3, 2)
+    if not all((3 in bcs[a]) for a in range(3)):
+        return  # spectral form, or a mix the oracle refuses
+    from .lgf import lgf_table
+    ext = tuple(2 * int(v) + 1 for v in n)
+    key = (ext, tuple(float(v) for v in h))
+    if key not in _lgf_keep:
+        _lgf_keep.clear()
+        _lgf_keep[key] = lgf_table(ext, h)
+    t = _lgf_keep[key]
+    lib().oracle_set_lgf(_dp(t), ext[0], ext[1], ext[2])
+
+
 def solve(rhs, n, h, bc, layout, green=0, kind=0, mode=FAST):
     """Solve lap(u) = f (kind 0) or lap(u) = curl(f) (kind 1: spectral derivative; 2, 3, 4:
     finite-difference derivative of order 2, 4, 6).
@@ -147,6 +173,7 @@ def solve(rhs, n, h, bc, layout, green=0, kind=0, mode=FAST):
     ncomp = 3 if kind >= 1 else 1
     rhs = np.ascontiguousarray(rhs, dtype=np.float64).reshape((ncomp,) + shp)
     out = np.empty_like(rhs)
+    _prepare_lgf(n, h, bc, green)
     _check(lib().oracle_solve(_ip(n), _dp(h), _ip(bc), layout, green, kind, mode, _dp(rhs), _dp(out)))
     return out if kind >= 1 else out[0]
 
@@ -159,6 +186,7 @@ def direct_points(rhs, n, h, bc, layout, points, green=0):
     rhs = np.ascontiguousarray(rhs, dtype=np.float64).reshape(shp)
     pts = np.ascontiguousarray(np.asarray(points, dtype=np.int32).reshape(-1, 3))
     out = np.empty(len(pts))
+    _prepare_lgf(n, h, bc, green)
     _check(lib().oracle_direct_points(_ip(n), _dp(h), _ip(bc), layout, green, _dp(rhs), len(pts),
                                       pts.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dp(out)))
     return out
@@ -176,6 +204,7 @@ def green_spectrum(n, h, bc, layout, green=0, mode=FAST):
     n, h, bc = _prep(n, h, bc)
     dx, dy, dz = spectral_dims(n, h, bc, layout)
     out = np.empty((dz, dy, dx), dtype=np.complex128)
+    _prepare_lgf(n, h, bc, green)
     _check(lib().oracle_green_spectrum(_ip(n), _dp(h), _ip(bc), layout, green, mode, _dp(out.view(np.float64))))
     return out
 

@@ -510,7 +510,19 @@ struct Green {
   double r_eq = 0.0;
   double eps = 0.0;      // HEJ2..10: regularisation length 2 h
   double kc = 0.0;       // HEJ0: spectral cut-off pi / h
+  // LGF2 (variant 8): the lattice Green's function at integer offsets 0 .. lgf_n[a] - 1
+  // along each axis (x fastest), supplied by the caller (oracle/lgf.py)
+  const double* lgf = nullptr;
+  long lgf_n[3] = {0, 0, 0};
+  double lattice(long m0, long m1, long m2) const {
+    m0 = std::labs(m0);
+    m1 = std::labs(m1);
+    m2 = std::labs(m2);
+    if (!lgf || m0 >= lgf_n[0] || m1 >= lgf_n[1] || m2 >= lgf_n[2]) return std::nan("");
+    return lgf[m0 + lgf_n[0] * (m1 + lgf_n[1] * m2)];
+  }
   double value(double rho, double k) const {
+    if (variant == 8) return std::nan("");  // LGF2: sampled by offset (lattice) or symbol
     if (variant >= 2) return hej(rho, k);
     if (du == 3) {
       if (rho > 0) return -1.0 / (4.0 * kPi * rho);
@@ -601,13 +613,17 @@ struct Problem {
                  // the finite-difference derivative of order 2 / 4 / 6 (Sec. V)
 };
 
+// The lattice Green's function table of the next solves (oracle_set_lgf).
+const double* g_lgf = nullptr;
+long g_lgf_n[3] = {0, 0, 0};
+
 int make_problem(const int* n, const double* h, const int* bc, int layout, int green, int kind,
                  Problem* P) {
   for (int a = 0; a < 3; ++a) {
     const int rc = make_axis(n[a], h[a], layout, bc[2 * a], bc[2 * a + 1], &P->ax[a]);
     if (rc) return rc;
   }
-  if (green < 0 || green > 7) return -3;
+  if (green < 0 || green > 8) return -3;
   if (kind < 0 || kind > 4) return -3;
   P->kind = kind;
   if (kind >= 1)
@@ -622,6 +638,19 @@ int make_problem(const int* n, const double* h, const int* bc, int layout, int g
   P->g.cellvol = vol;
   if (P->du == 3) P->g.r_eq = std::cbrt(3.0 * vol / (4.0 * kPi));
   if (P->du == 2) P->g.r_eq = std::sqrt(vol / kPi);
+  if (green == 8) {
+    // lattice Green's function: three convolution directions (the table covers offsets
+    // up to 2N along each) or none (the inverse of the second-difference symbol)
+    if (P->du == 1 || P->du == 2) return -3;
+    if (P->du == 3) {
+      if (!g_lgf) return -6;
+      for (int a = 0; a < 3; ++a)
+        if (g_lgf_n[a] < 2L * P->ax[a].N + 1) return -6;
+      P->g.lgf = g_lgf;
+      for (int a = 0; a < 3; ++a) P->g.lgf_n[a] = g_lgf_n[a];
+    }
+    return 0;
+  }
   if (green >= 2) {
     // regularised kernels: three convolution directions or none; the grid spacing is
     // the cube root of the cell volume (the spacing itself on isotropic grids)
@@ -654,20 +683,27 @@ std::vector<cd> green_spectrum(const Problem& P, int mode) {
     for (long y = 0; y < ext[1]; ++y)
       for (long x = 0; x < ext[0]; ++x) {
         const long idx[3] = {x, y, z};
-        double k2 = 0.0, r2 = 0.0;
+        double k2 = 0.0, r2 = 0.0, s2 = 0.0;
+        long off[3] = {0, 0, 0};
         for (int a = 0; a < 3; ++a) {
           const Axis& A = P.ax[a];
           if (!A.unb) {
             const double w = omega(A, (int)idx[a], false);
             k2 += w * w;
+            const double d = 2.0 * std::sin(0.5 * w * A.h) / A.h;  // second-difference symbol
+            s2 += d * d;
           } else {
             long m = idx[a];
             if (A.cls == C_UU && m > A.N) m = 2 * A.N - m;  // symmetrised about L
+            off[a] = m;
             const double d = m * A.h;
             r2 += d * d;
           }
         }
-        G[x + ext[0] * (y + ext[1] * z)] = P.g.value(std::sqrt(r2), std::sqrt(k2));
+        double gv;
+        if (P.g.variant == 8) gv = P.du == 3 ? P.g.lattice(off[0], off[1], off[2]) : (s2 > 0.0 ? -1.0 / s2 : 0.0);
+        else gv = P.g.value(std::sqrt(r2), std::sqrt(k2));
+        G[x + ext[0] * (y + ext[1] * z)] = gv;
       }
   // transform the convolution directions
   Dims cur = ds;
@@ -841,12 +877,18 @@ int solve_direct(const Problem& P, const double* rhs, double* out) {
     for (long y = 0; y < n1; ++y)
       for (long x = 0; x < n0; ++x) {
         const long idx[3] = {x, y, z};
-        double k2 = 0.0;
+        double k2 = 0.0, s2 = 0.0;
         for (int ax = 0; ax < 3; ++ax)
-          if (!P.ax[ax].unb) { const double w = omega(P.ax[ax], (int)idx[ax], false); k2 += w * w; }
+          if (!P.ax[ax].unb) {
+            const double w = omega(P.ax[ax], (int)idx[ax], false);
+            k2 += w * w;
+            const double d = 2.0 * std::sin(0.5 * w * P.ax[ax].h) / P.ax[ax].h;
+            s2 += d * d;
+          }
         const double k = std::sqrt(k2);
         if (P.du == 0) {
-          b[x + n0 * (y + n1 * z)] = a[x + n0 * (y + n1 * z)] * P.g.value(0.0, k);
+          const double gv = P.g.variant == 8 ? (s2 > 0.0 ? -1.0 / s2 : 0.0) : P.g.value(0.0, k);
+          b[x + n0 * (y + n1 * z)] = a[x + n0 * (y + n1 * z)] * gv;
           continue;
         }
         // target position in the convolution directions
@@ -863,17 +905,20 @@ int solve_direct(const Problem& P, const double* rhs, double* out) {
           for (int s1 = 0; s1 < sz1; ++s1)
             for (int s0 = 0; s0 < sz0; ++s0) {
               const int ss[3] = {s0, s1, s2};
-              long jj[3];
+              long jj[3], off[3] = {0, 0, 0};
               double r2 = 0.0, sign = 1.0;
               for (int ax = 0; ax < 3; ++ax) {
                 if (!P.ax[ax].unb) { jj[ax] = idx[ax]; continue; }
                 const Src& S = src[ax][ss[ax]];
                 jj[ax] = S.j;
                 const double d = xt[ax] - S.x;
+                off[ax] = std::lround(d / P.ax[ax].h);
                 r2 += d * d;
                 sign *= S.sign;
               }
-              acc += sign * P.g.value(std::sqrt(r2), k) * a[jj[0] + n0 * (jj[1] + n1 * jj[2])];
+              const double gv = P.g.variant == 8 ? P.g.lattice(off[0], off[1], off[2])
+                                                 : P.g.value(std::sqrt(r2), k);
+              acc += sign * gv * a[jj[0] + n0 * (jj[1] + n1 * jj[2])];
             }
         b[x + n0 * (y + n1 * z)] = acc * cellvol;
       }
@@ -963,7 +1008,11 @@ int direct_points(const Problem& P, const double* rhs, int npts, const int* pts,
         const double syz = Y.sign * Z.sign;
         for (const Src& X : src[0]) {
           const double dx = xt[0] - X.x;
-          part += syz * X.sign * P.g.value(std::sqrt(dx * dx + dy * dy + dz * dz), 0.0) * row[X.j];
+          const double gv = P.g.variant == 8
+                                ? P.g.lattice(std::lround(dx / P.ax[0].h), std::lround(dy / P.ax[1].h),
+                                              std::lround(dz / P.ax[2].h))
+                                : P.g.value(std::sqrt(dx * dx + dy * dy + dz * dz), 0.0);
+          part += syz * X.sign * gv * row[X.j];
         }
       }
       acc += part;
@@ -979,6 +1028,15 @@ int direct_points(const Problem& P, const double* rhs, int npts, const int* pts,
 // C interface (ctypes)
 // ---------------------------------------------------------------------------------
 extern "C" {
+
+// LGF2: the lattice Green's function at integer offsets [n2][n1][n0] (x fastest) used by
+// the following solves with three convolution directions; the caller keeps it alive.
+void oracle_set_lgf(const double* table, long n0, long n1, long n2) {
+  g_lgf = table;
+  g_lgf_n[0] = n0;
+  g_lgf_n[1] = n1;
+  g_lgf_n[2] = n2;
+}
 
 int oracle_fft(int n, const double* in, double* out, int sign) {
   if (n < 1) return -2;
