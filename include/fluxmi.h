@@ -58,7 +58,12 @@ typedef enum { FM_CELL = 0, FM_NODE = 1 } fm_layout;
  * eps = 2 h with h = (hx hy hz)^(1/3) (the reading that reproduces the printed errors of
  * every HEJ kernel).  These need three unbounded directions (the real-space form
  * -(1/4 pi r)[erf(r / (sqrt 2 eps)) + ...], finite at r = 0) or none (the spectral form
- * -zeta_hat(k) / k^2); other mixes return FM_E_KIND. */
+ * -zeta_hat(k) / k^2); other mixes return FM_E_KIND.
+ * FM_GREEN_LGF2 (Sec. IV, the lattice Green's function): the Green's function of the
+ * second-difference (7-point) Laplacian, so that the solve inverts that discrete operator
+ * exactly: sampled at the integer offsets of three unbounded-type directions, or
+ * -1 / sum_a (2 sin(k_a h_a / 2) / h_a)^2 with no unbounded direction; other mixes return
+ * FM_E_KIND. */
 typedef enum {
   FM_GREEN_CHAT2 = 0,
   FM_GREEN_CHAT2_VOL = 1,
@@ -67,7 +72,8 @@ typedef enum {
   FM_GREEN_HEJ6 = 4,
   FM_GREEN_HEJ8 = 5,
   FM_GREEN_HEJ10 = 6,
-  FM_GREEN_HEJ0 = 7
+  FM_GREEN_HEJ0 = 7,
+  FM_GREEN_LGF2 = 8
 } fm_green;
 
 /* Arithmetic of the transforms.  FM_F32 plans take their twiddles and Green's

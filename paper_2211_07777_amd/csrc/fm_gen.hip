@@ -188,8 +188,116 @@ __device__ double hej_value(const GreenGen& g, double r, double k) {
   return -exp(-s) * sum / (k * k);
 }
 
+// ---------------------------------------------------------------------------------
+// Lattice Green's function (FM_GREEN_LGF2): the Green's function of the second-difference
+// Laplacian.  With the discrete heat kernel exp(-2t/h^2) I_n(2t/h^2) of each axis,
+//   G(n) = -(1 / prod h) int_0^inf prod_a exp(-x_a) I_{n_a}(x_a) dt,   x_a = 2 t / h_a^2.
+// The integral is taken with the trapezoidal rule in u = ln t after subtracting
+// prod h (4 pi (t + c))^(-3/2) (the far field, integrated in closed form).  The scaled
+// Bessel values of every node come from the power series (x < 1), Miller's backward
+// recurrence normalised by exp(x) = I_0 + 2 sum I_k (moderate x), or the large-argument
+// expansion (x >= 40 (n_max^2 + 10)).
+// ---------------------------------------------------------------------------------
+__device__ void scaled_bessel_row(double x, int count, double* row) {
+  const int nmax = count - 1;
+  if (x < 1.0) {
+    // e^{-x} (x/2)^n sum_j (x^2/4)^j / (j! (n + j)!)
+    const double q = 0.25 * x * x, ex = exp(-x);
+    double lead = 1.0;  // (x/2)^n / n!
+    for (int n = 0; n <= nmax; ++n) {
+      if (n > 0) lead *= 0.5 * x / n;
+      double term = 1.0, sum = 1.0;
+      for (int j = 1; j < 40; ++j) {
+        term *= q / (j * (double)(n + j));
+        sum += term;
+        if (term < 1e-18 * sum) break;
+      }
+      row[n] = ex * lead * sum;
+    }
+    return;
+  }
+  if (x >= 40.0 * ((double)nmax * nmax + 10.0)) {
+    const double pre = 1.0 / sqrt(2.0 * 3.14159265358979323846 * x);
+    for (int n = 0; n <= nmax; ++n) {
+      const double mu = 4.0 * (double)n * n;
+      double term = 1.0, sum = 1.0;
+      for (int k = 1; k < 12; ++k) {
+        term *= -(mu - (2.0 * k - 1.0) * (2.0 * k - 1.0)) / (k * 8.0 * x);
+        sum += term;
+      }
+      row[n] = pre * sum;
+    }
+    return;
+  }
+  // backward recurrence I_{n-1} = I_{n+1} + (2n / x) I_n from far above n_max
+  const int n0 = (int)sqrt((double)nmax * nmax + 80.0 * x) + 24;
+  double ip1 = 0.0, in = 1e-280, norm = 0.0;
+  for (int n = n0; n >= 1; --n) {
+    const double im1 = ip1 + (2.0 * n / x) * in;
+    // in is I_n, im1 is I_{n-1}
+    norm += 2.0 * in;
+    if (n <= nmax) row[n] = in;
+    ip1 = in;
+    in = im1;
+    if (fabs(in) > 1e250) {  // rescale everything held so far
+      const double s = 1e-250;
+      in *= s;
+      ip1 *= s;
+      norm *= s;
+      for (int m = n; m <= nmax && m <= n0; ++m) row[m] *= s;
+    }
+  }
+  norm += in;  // I_0
+  row[0] = in;
+  const double inv = 1.0 / norm;
+  for (int n = 0; n <= nmax; ++n) row[n] *= inv;
+}
+
+__global__ void lgf_bessel_kernel(double* A, LgfGen g) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= 3 * g.K) return;
+  const int a = id / g.K, k = id % g.K;
+  const double t = exp(g.u_lo + k * g.du);
+  scaled_bessel_row(2.0 * t / (g.h[a] * g.h[a]), g.nA[a], A + ((size_t)a * g.K + k) * g.stride);
+}
+
+// Node weights du t_k and far-field values prod h (4 pi (t_k + c))^(-3/2), k < K.
+__global__ void lgf_weight_kernel(double* W, LgfGen g) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= g.K) return;
+  const double pi = 3.14159265358979323846;
+  const double t = exp(g.u_lo + k * g.du);
+  W[k] = g.du * t;
+  W[g.K + k] = g.h[0] * g.h[1] * g.h[2] * pow(4.0 * pi * (t + g.c), -1.5);
+}
+
+__global__ void lgf_sample_kernel(double* S, LgfGen g, const double* __restrict__ A,
+                                  const double* __restrict__ W) {
+  const int64_t total = (int64_t)g.nA[0] * g.nA[1] * g.nA[2];
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  int64_t r = e;
+  const int i2 = (int)(r % g.nA[2]);
+  r /= g.nA[2];
+  const int i1 = (int)(r % g.nA[1]);
+  const int i0 = (int)(r / g.nA[1]);
+  const double pi = 3.14159265358979323846;
+  const double ph = g.h[0] * g.h[1] * g.h[2];
+  const double* a0 = A + i0;
+  const double* a1 = A + (size_t)g.K * g.stride + i1;
+  const double* a2 = A + (size_t)2 * g.K * g.stride + i2;
+  double acc = 0.0;
+  for (int k = 0; k < g.K; ++k) {
+    const size_t o = (size_t)k * g.stride;
+    acc += W[k] * (a0[o] * a1[o] * a2[o] - W[g.K + k]);
+  }
+  acc += ph * 2.0 * pow(4.0 * pi, -1.5) / sqrt(g.c);
+  S[e] = -acc / ph;
+}
+
 __device__ double green_value(const GreenGen& g, double rho, double k) {
   const double pi = 3.14159265358979323846;
+  if (g.variant == 8) return nan("");  // LGF2 is sampled by lgf_sample_kernel
   if (g.variant >= 2) return hej_value(g, rho, k);
   if (g.du == 3) {
     if (rho > 0.0) return -1.0 / (4.0 * pi * rho);
@@ -222,7 +330,7 @@ __global__ void green_sample_kernel(double* S, GreenGen g) {
   r /= g.n[2];
   idx[1] = (int)(r % g.n[1]);
   idx[0] = (int)(r / g.n[1]);
-  double r2 = 0.0, k2 = 0.0;
+  double r2 = 0.0, k2 = 0.0, s2 = 0.0;
   for (int a = 0; a < 3; ++a) {
     if (g.unb[a]) {
       const double dd = idx[a] * g.h[a];
@@ -230,7 +338,13 @@ __global__ void green_sample_kernel(double* S, GreenGen g) {
     } else {
       const double w = g.dw[a] * (idx[a] + g.shift[a]);
       k2 += w * w;
+      const double sd = 2.0 * sin(0.5 * w * g.h[a]) / g.h[a];  // second-difference symbol
+      s2 += sd * sd;
     }
+  }
+  if (g.variant == 8) {  // LGF2 without convolution directions: the inverse symbol
+    S[e] = s2 > 0.0 ? -1.0 / s2 : 0.0;
+    return;
   }
   S[e] = green_value(g, sqrt(r2), sqrt(k2));
 }
@@ -336,6 +450,19 @@ hipError_t launch_wave_twiddles(void* out, int M, int E, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(wave_twiddle_kernel<T>, dim3((n + 255) / 256), dim3(256), 0, st,
                      reinterpret_cast<cpx<T>*>(out), M, E);
+  return hipGetLastError();
+}
+
+// A: 3 K stride doubles (Bessel rows), W: 2 K doubles (node weights, far field).
+hipError_t launch_lgf(double* S, double* A, double* W, const LgfGen& g, hipStream_t st) {
+  hipLaunchKernelGGL(lgf_bessel_kernel, dim3((3 * g.K + 63) / 64), dim3(64), 0, st, A, g);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(lgf_weight_kernel, dim3((g.K + 255) / 256), dim3(256), 0, st, W, g);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t total = (int64_t)g.nA[0] * g.nA[1] * g.nA[2];
+  hipLaunchKernelGGL(lgf_sample_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, S, g, A, W);
   return hipGetLastError();
 }
 

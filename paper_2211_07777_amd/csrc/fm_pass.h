@@ -272,4 +272,13 @@ struct GreenGen {
   double eps, kc;            // regularised kernels: smoothing length, spectral cut-off
 };
 
+// Lattice Green's function (LGF2) quadrature: nodes t_k = exp(u_lo + k du), k < K, and
+// per table axis the scaled Bessel values exp(-x) I_n(x), x = 2 t_k / h^2, n < nA.
+struct LgfGen {
+  int32_t K, stride;         // nodes, row stride of the Bessel table (>= max nA)
+  int32_t nA[3];             // offsets per table axis
+  double u_lo, du, c;        // log-t grid; far-field subtraction constant
+  double h[3];               // spacing per table axis
+};
+
 }  // namespace fm

@@ -31,6 +31,7 @@ template <typename T> hipError_t launch_wave_twiddles(void* out, int M, int E, h
 bool is_fast_len(int M);
 
 hipError_t launch_green_sample(double* S, const GreenGen& g, hipStream_t st);
+hipError_t launch_lgf(double* S, double* A, double* W, const LgfGen& g, hipStream_t st);
 template <typename T>
 hipError_t launch_green_final(void* G, const double* S, const int F[3], const int n[3],
                               const int off[3], double scale, hipStream_t st);
@@ -672,7 +673,34 @@ int make_tables_and_green(fm_plan_s* p, hipStream_t st, bool deferred) {
   if (hipMalloc(&S, sizeof(double) * ns) != hipSuccess) return FM_E_NOMEM;
   p->gen_free.push_back(S);
   int rc = FM_OK;
-  FM_HIP(fm::launch_green_sample(S, g, st));
+  if (p->green == FM_GREEN_LGF2 && du == 3) {
+    // lattice Green's function: Bessel rows of the quadrature nodes, then the samples
+    fm::LgfGen lg{};
+    int nmax = 1;
+    double hmin = 1e300, hmax = 0.0;
+    for (int i = 0; i < 3; ++i) {
+      lg.nA[i] = Fs[i];
+      lg.h[i] = g.h[i];
+      nmax = std::max(nmax, Fs[i]);
+      hmin = std::min(hmin, g.h[i]);
+      hmax = std::max(hmax, g.h[i]);
+    }
+    lg.stride = nmax;
+    lg.du = 0.125;
+    lg.c = 2.0 * hmax * hmax;
+    lg.u_lo = std::log(hmin * hmin) - 38.0;
+    const double u_hi = std::log(hmax * hmax * (1.0 + (double)nmax * nmax)) + 28.0;
+    lg.K = (int)std::ceil((u_hi - lg.u_lo) / lg.du) + 1;
+    double* A = nullptr;
+    double* W = nullptr;
+    if (hipMalloc(&A, sizeof(double) * 3 * (size_t)lg.K * lg.stride) != hipSuccess) return FM_E_NOMEM;
+    p->gen_free.push_back(A);
+    if (hipMalloc(&W, sizeof(double) * 2 * (size_t)lg.K) != hipSuccess) return FM_E_NOMEM;
+    p->gen_free.push_back(W);
+    FM_HIP(fm::launch_lgf(S, A, W, lg, st));
+  } else {
+    FM_HIP(fm::launch_green_sample(S, g, st));
+  }
   int64_t sstr[3] = {(int64_t)Fs[1] * Fs[2], Fs[2], 1};
   p->gen_desc.assign(3, fm::PassDesc{});  // host copies stay alive until the copies ran
   fm::PassDesc* gdesc = p->gen_desc.data();
@@ -1445,7 +1473,7 @@ namespace {
 
 int check_enums(int layout, int green, int prec, int kind, int ncomp) {
   if (layout != FM_CELL && layout != FM_NODE) return FM_E_KIND;
-  if (green < FM_GREEN_CHAT2 || green > FM_GREEN_HEJ0) return FM_E_KIND;
+  if (green < FM_GREEN_CHAT2 || green > FM_GREEN_LGF2) return FM_E_KIND;
   if (prec != FM_F64 && prec != FM_F32) return FM_E_KIND;
   if (kind < FM_POISSON || kind > FM_BIOT_SAVART_FD6) return FM_E_KIND;
   if (ncomp < 1 || ncomp > 64) return FM_E_KIND;

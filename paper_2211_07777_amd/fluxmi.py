@@ -18,6 +18,7 @@ EVEN, ODD, PER, UNB = 0, 1, 2, 3
 CELL, NODE = 0, 1
 CHAT2, CHAT2_VOL = 0, 1
 HEJ2, HEJ4, HEJ6, HEJ8, HEJ10, HEJ0 = 2, 3, 4, 5, 6, 7  # regularised kernels (Sec. IV)
+LGF2 = 8  # lattice Green's function of the second-difference Laplacian (Sec. IV)
 F64, F32 = 0, 1
 POISSON, BIOT_SAVART, BIOT_SAVART_FD2, BIOT_SAVART_FD4, BIOT_SAVART_FD6 = 0, 1, 2, 3, 4
 CLASS_NAMES = ["P", "EE", "OO", "EO", "OE", "UU", "EU", "OU", "UE", "UO"]

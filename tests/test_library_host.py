@@ -67,7 +67,7 @@ def test_rejects_bad_arguments():
 
 
 def test_regularised_kernels_need_three_or_no_unbounded_directions():
-    for g in (F.HEJ2, F.HEJ4, F.HEJ6, F.HEJ8, F.HEJ10, F.HEJ0):
+    for g in (F.HEJ2, F.HEJ4, F.HEJ6, F.HEJ8, F.HEJ10, F.HEJ0, F.LGF2):
         F.plan_inspect([8, 8, 8], [0.1] * 3, [[3, 3]] * 3, 0, g)
         F.plan_inspect([8, 8, 8], [0.1] * 3, [[0, 3], [3, 1], [3, 3]], 1, g)
         F.plan_inspect([8, 8, 8], [0.1] * 3, [[2, 2], [0, 1], [1, 1]], 0, g)
@@ -76,7 +76,7 @@ def test_regularised_kernels_need_three_or_no_unbounded_directions():
                 F.plan_inspect([8, 8, 8], [0.1] * 3, bc, 0, g)
             assert e.value.status == -4
     with pytest.raises(F.FluxmiError) as e:
-        F.plan_inspect([8, 8, 8], [0.1] * 3, [[3, 3]] * 3, 0, 8)
+        F.plan_inspect([8, 8, 8], [0.1] * 3, [[3, 3]] * 3, 0, 9)
     assert e.value.status == -4
 
 
