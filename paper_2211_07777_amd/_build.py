@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfluxmi.so")
-HEADERS = ["fm_pass.h", "fm_device.h", "fm_wave.h", "fm_launch.h", "fm_internal.h"]
+HEADERS = ["fm_pass.h", "fm_device.h", "fm_wave.h", "fm_launch.h", "fm_internal.h", "fm_special.h"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -53,7 +53,7 @@ def _compile(unit, force=True):
     out = os.path.join(OBJ, obj)
     if not force and os.path.exists(out):
         device = src.endswith(("fm_inst.hip", "fm_gen.hip"))  # include fm_device.h only
-        heads = ["fm_pass.h", "fm_device.h", "fm_wave.h", "fm_launch.h"] if device else ["fm_pass.h", "fm_internal.h"]
+        heads = ["fm_pass.h", "fm_device.h", "fm_wave.h", "fm_launch.h", "fm_special.h"] if device else ["fm_pass.h", "fm_internal.h"]
         deps = [src] + [os.path.join(CSRC, h) for h in heads] + [os.path.abspath(__file__)]
         if not device:
             deps.append(os.path.join(os.path.dirname(HERE), "include", "fluxmi.h"))
