@@ -219,8 +219,17 @@ int fm_solve_batched(int count, const fm_plan* plans, const void* const* rhs_dev
  * rounding level only: two real lines share one complex FFT, and which lines are paired
  * follows the tiling.  workspace_dev as for fm_solve (NULL: the plan's own);
  * the call allocates two scratch arrays of the user shape and synchronises hip_stream.
- * Not to be called while solves with this plan are in flight. */
+ * Not to be called while solves with this plan are in flight.
+ * With the environment variable FLUXMI_TUNE_CACHE naming a file, the call first looks
+ * up the plan's problem (device name and CU count, precision, kind, components, layout,
+ * Green's function, sizes and boundary conditions) there and, when an entry validates
+ * for this plan, applies it without timing anything; otherwise it tunes and appends the
+ * result as one text line.  Concurrent calls in one process are serialised on the file. */
 int fm_plan_tune(fm_plan p, void* workspace_dev, void* hip_stream);
+
+/* *from_cache = 1 when the last fm_plan_tune of p applied a FLUXMI_TUNE_CACHE entry,
+ * else 0. */
+int fm_plan_tuned_from_cache(fm_plan p, int* from_cache);
 
 /* Device memory held by the plan's tables (Green's spectrum, twiddles, descriptors),
  * not counting its own workspace. */

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <string>
 #include <new>
 #include <vector>
 
@@ -259,6 +260,7 @@ struct fm_plan_s {
   std::map<int, void*> tw;
   std::map<int, void*> stw;
   std::map<int, void*> tw64;
+  int tuned_from_cache = 0;  // the last fm_plan_tune applied a FLUXMI_TUNE_CACHE entry
   std::map<int, void*> wtw;  // stage twiddles of the per-wavefront kernels, by (M << 5) | E
   void* dtab = nullptr;      // central-difference symbols of the curl (line, b, c tables)
   void* ws_internal = nullptr;
@@ -1781,9 +1783,98 @@ bool retile(const fm_plan_s* p, int i, int bmax, int mode, fm::PassDesc* out) {
   return true;
 }
 
+extern "C++" {
+namespace {
+
+// A tiling as fm_plan_tiling reports it, validated pass by pass and applied.
+int apply_tiling(fm_plan p, const int lines_per_tile[5], const int persist[5], hipStream_t st) {
+  fm::PassDesc next[5];
+  for (int i = 0; i < 5; ++i) {
+    const int mode = persist[i];
+    if (lines_per_tile[i] < 1 || mode < 0 || mode > 4) return FM_E_ARG;
+    if (!retile(p, i, lines_per_tile[i], mode, &next[i])) return FM_E_ARG;
+    // exactly the requested tiling (retile takes the largest tile up to the bound)
+    if (next[i].B != lines_per_tile[i] || launch_mode(next[i], p->elem) != mode) return FM_E_ARG;
+  }
+  for (int i = 0; i < 5; ++i) p->pass[i] = next[i];
+  FM_HIP(hipMemcpyAsync(p->dpass, p->pass, sizeof(fm::PassDesc) * 5, hipMemcpyHostToDevice, st));
+  FM_HIP(hipStreamSynchronize(st));
+  return FM_OK;
+}
+
+// Tuning cache (FLUXMI_TUNE_CACHE): one line per tuned problem,
+//   <device>/<CUs> p<prec> k<kind> c<ncomp> l<layout> g<green> n<nx,ny,nz> b<6 faces> B<5> M<5>
+// read before tuning (a valid entry is applied instead of timing) and appended after.
+std::mutex g_tune_cache_mu;
+
+std::string tune_key(const fm_plan_s* p) {
+  int dev = 0;
+  hipDeviceProp_t prop{};
+  std::string arch = "unknown";
+  int cus = 0;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    arch = prop.gcnArchName;
+    cus = prop.multiProcessorCount;
+  }
+  for (char& ch : arch)
+    if (ch == ' ' || ch == ':') ch = '_';
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "%s/%d p%d k%d c%d l%d g%d n%d,%d,%d b%d,%d,%d,%d,%d,%d", arch.c_str(), cus,
+                p->prec, p->kind, p->ncomp, p->layout, p->green, p->n[0], p->n[1], p->n[2], p->bc[0][0],
+                p->bc[0][1], p->bc[1][0], p->bc[1][1], p->bc[2][0], p->bc[2][1]);
+  return buf;
+}
+
+bool tune_cache_lookup(const char* path, const std::string& key, int lines[5], int modes[5]) {
+  std::lock_guard<std::mutex> lock(g_tune_cache_mu);
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[512];
+  bool found = false;
+  while (std::fgets(line, sizeof(line), f)) {
+    const size_t kl = key.size();
+    if (std::strncmp(line, key.c_str(), kl) != 0 || line[kl] != ' ') continue;
+    int b[5], m[5];
+    if (std::sscanf(line + kl, " B%d,%d,%d,%d,%d M%d,%d,%d,%d,%d", &b[0], &b[1], &b[2], &b[3], &b[4], &m[0],
+                    &m[1], &m[2], &m[3], &m[4]) == 10) {
+      for (int i = 0; i < 5; ++i) {
+        lines[i] = b[i];
+        modes[i] = m[i];
+      }
+      found = true;  // the last entry of a key wins
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+void tune_cache_store(const char* path, const std::string& key, const fm_plan_s* p) {
+  std::lock_guard<std::mutex> lock(g_tune_cache_mu);
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s B%d,%d,%d,%d,%d M%d,%d,%d,%d,%d\n", key.c_str(), p->pass[0].B, p->pass[1].B, p->pass[2].B,
+               p->pass[3].B, p->pass[4].B, launch_mode(p->pass[0], p->elem), launch_mode(p->pass[1], p->elem),
+               launch_mode(p->pass[2], p->elem), launch_mode(p->pass[3], p->elem), launch_mode(p->pass[4], p->elem));
+  std::fclose(f);
+}
+
+}  // namespace
+}  // extern "C++"
+
 int fm_plan_tune(fm_plan p, void* workspace_dev, void* hip_stream) {
   if (!p) return FM_E_NULL;
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  const char* cache = std::getenv("FLUXMI_TUNE_CACHE");
+  std::string key;
+  if (cache && *cache) {
+    key = tune_key(p);
+    int lines[5], modes[5];
+    if (tune_cache_lookup(cache, key, lines, modes) && apply_tiling(p, lines, modes, st) == FM_OK) {
+      p->tuned_from_cache = 1;
+      return FM_OK;
+    }
+  }
+  p->tuned_from_cache = 0;
   char* ws = reinterpret_cast<char*>(workspace_dev);
   if (!ws && !(ws = own_workspace(p))) return FM_E_NOMEM;
   // scratch right-hand side and output (their values do not change the timing)
@@ -1856,6 +1947,7 @@ int fm_plan_tune(fm_plan p, void* workspace_dev, void* hip_stream) {
   if (e1) (void)hipEventDestroy(e1);
   (void)hipFree(rhs);
   (void)hipFree(out);
+  if (rc == FM_OK && cache && *cache) tune_cache_store(cache, key, p);
   return rc;
 }
 
@@ -1877,18 +1969,12 @@ int fm_plan_tiling(fm_plan p, int lines_per_tile[5], int tiles[5], int persist[5
 
 int fm_plan_set_tiling(fm_plan p, const int lines_per_tile[5], const int persist[5], void* hip_stream) {
   if (!p || !lines_per_tile || !persist) return FM_E_NULL;
-  fm::PassDesc next[5];
-  for (int i = 0; i < 5; ++i) {
-    const int mode = persist[i];
-    if (lines_per_tile[i] < 1 || mode < 0 || mode > 4) return FM_E_ARG;
-    if (!retile(p, i, lines_per_tile[i], mode, &next[i])) return FM_E_ARG;
-    // exactly the requested tiling (retile takes the largest tile up to the bound)
-    if (next[i].B != lines_per_tile[i] || launch_mode(next[i], p->elem) != mode) return FM_E_ARG;
-  }
-  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
-  for (int i = 0; i < 5; ++i) p->pass[i] = next[i];
-  FM_HIP(hipMemcpyAsync(p->dpass, p->pass, sizeof(fm::PassDesc) * 5, hipMemcpyHostToDevice, st));
-  FM_HIP(hipStreamSynchronize(st));
+  return apply_tiling(p, lines_per_tile, persist, reinterpret_cast<hipStream_t>(hip_stream));
+}
+
+int fm_plan_tuned_from_cache(fm_plan p, int* from_cache) {
+  if (!p || !from_cache) return FM_E_NULL;
+  *from_cache = p->tuned_from_cache;
   return FM_OK;
 }
 

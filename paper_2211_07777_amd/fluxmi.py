@@ -29,7 +29,7 @@ EXPORTED = [
     "fm_plan_tune", "fm_plan_tiling", "fm_plan_device_bytes",
     "fm_server_create", "fm_server_submit", "fm_server_progress", "fm_server_wait_all",
     "fm_server_get_stats", "fm_server_destroy", "fm_solve_static", "fm_plan_set_tiling",
-    "fm_plan_spectrum_layout", "fm_fft_forward", "fm_fft_backward",
+    "fm_plan_spectrum_layout", "fm_fft_forward", "fm_fft_backward", "fm_plan_tuned_from_cache",
 ]
 STATIC_WORKSPACE_BYTES = 128 << 20  # FM_STATIC_WORKSPACE_BYTES
 
@@ -100,6 +100,7 @@ def library():
     L.fm_plan_tune.argtypes = [vp, vp, vp]
     L.fm_plan_tiling.argtypes = [vp, ip, ip, ip]
     L.fm_plan_set_tiling.argtypes = [vp, ip, ip, vp]
+    L.fm_plan_tuned_from_cache.argtypes = [vp, ip]
     L.fm_plan_device_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
     L.fm_server_create.argtypes = [ctypes.POINTER(vp), ctypes.c_size_t, ctypes.c_size_t, ctypes.c_int,
                                    ctypes.c_int]
@@ -286,9 +287,16 @@ class Plan:
         _check(library().fm_plan_tune(self._h, ws, _stream_ptr(stream)), "fm_plan_tune")
         return self.tiling()
 
+    def tuned_from_cache(self):
+        """True when the last tune() applied an entry of the FLUXMI_TUNE_CACHE file."""
+        v = ctypes.c_int()
+        _check(library().fm_plan_tuned_from_cache(self._h, ctypes.byref(v)), "fm_plan_tuned_from_cache")
+        return bool(v.value)
+
     def tiling(self):
         """(lines per tile, tiles, launch mode) of the five passes; mode 1 = persistent
-        grid, 0 = one tile per workgroup with LDS tables, 2 = with global tables."""
+        grid, 0 = one tile per workgroup with LDS tables, 2 = with global tables, 3 / 4 =
+        the per-wavefront kernels with 16 / 8 values per lane."""
         b, t, q = (ctypes.c_int * 5)(), (ctypes.c_int * 5)(), (ctypes.c_int * 5)()
         _check(library().fm_plan_tiling(self._h, b, t, q), "fm_plan_tiling")
         return {"lines_per_tile": list(b), "tiles": list(t), "persistent": list(q)}

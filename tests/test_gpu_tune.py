@@ -52,3 +52,37 @@ def test_tuned_small_plans_batch_equals_single():
         assert torch.equal(s, o)
     for p in plans:
         p.close()
+
+
+def test_tuning_cache_round_trip(tmp_path, monkeypatch):
+    """FLUXMI_TUNE_CACHE: the first tune times and appends one line; a new plan of the same
+    problem applies that line without timing and gets the same tiling and the same
+    result; an entry that does not validate for the plan is ignored (the plan is tuned)."""
+    import torch
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("FLUXMI_TUNE_CACHE", str(path))
+    n, h, bc = [64, 48, 40], [0.02, 0.03, 0.025], [[2, 2], [0, 1], [3, 3]]
+    f = W.random_field(O.user_shape(n, O.NODE), 77)
+    a = F.Plan(n, h, bc, F.NODE, F.CHAT2, F.F32)
+    ta = a.tune()
+    assert not a.tuned_from_cache()
+    lines = path.read_text().splitlines()
+    assert len(lines) == 1 and " B" in lines[0] and " M" in lines[0]
+    b = F.Plan(n, h, bc, F.NODE, F.CHAT2, F.F32)
+    tb = b.tune()
+    assert b.tuned_from_cache() and tb == ta
+    ua, ub = gpu_solve(a, f), gpu_solve(b, f)
+    assert np.array_equal(ua, ub)
+    # a different problem has its own entry
+    c = F.Plan(n, h, bc, F.NODE, F.CHAT2, F.F64)
+    c.tune()
+    assert not c.tuned_from_cache() and len(path.read_text().splitlines()) == 2
+    # a corrupted tiling for this key is not applied
+    key = lines[0].split(" B")[0]
+    path.write_text(key + " B1000,1,1,1,1 M0,0,0,0,0\n")
+    d = F.Plan(n, h, bc, F.NODE, F.CHAT2, F.F32)
+    d.tune()
+    assert not d.tuned_from_cache()
+    for p in (a, b, c, d):
+        p.close()
+    torch.cuda.synchronize()
