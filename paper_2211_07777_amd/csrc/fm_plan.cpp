@@ -279,6 +279,33 @@ namespace {
 
 size_t round256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Device allocations of plan creation and tuning.  Test hook: with FLUXMI_FAIL_ALLOC=k the
+// k-th of them (counted from 1 since the variable last changed) reports out-of-memory, so
+// that every failure path of plan creation can be driven from the host.
+hipError_t plan_malloc_raw(void** ptr, size_t bytes) {
+  static std::mutex mu;
+  static std::string last;
+  static long count = 0;
+  const char* e = std::getenv("FLUXMI_FAIL_ALLOC");
+  if (e && *e) {
+    std::lock_guard<std::mutex> lock(mu);
+    if (last != e) {
+      last = e;
+      count = 0;
+    }
+    if (++count == std::atol(e)) {
+      *ptr = nullptr;
+      return hipErrorOutOfMemory;
+    }
+  }
+  return hipMalloc(ptr, bytes);
+}
+
+template <typename P>
+hipError_t plan_malloc(P** ptr, size_t bytes) {
+  return plan_malloc_raw(reinterpret_cast<void**>(ptr), bytes);
+}
+
 // multiplier m = ceil(2^32 / d): n / d == (n * m) >> 32 whenever n * d < 2^32
 uint64_t magic(int d) {
   const uint64_t dd = (uint64_t)std::max(d, 1);
@@ -555,7 +582,7 @@ int make_tables_and_green(fm_plan_s* p, hipStream_t st, bool deferred) {
     const int M = p->pass[i].M;
     if (p->tw.count(M)) continue;
     void* ptr = nullptr;
-    if (hipMalloc(&ptr, sizeof(T) * 2 * 4 * (size_t)M) != hipSuccess) return FM_E_NOMEM;
+    if (plan_malloc(&ptr, sizeof(T) * 2 * 4 * (size_t)M) != hipSuccess) return FM_E_NOMEM;
     p->tw[M] = ptr;
     p->table_bytes += sizeof(T) * 2 * 4 * (size_t)M;
     FM_HIP(fm::launch_twiddles<T>(ptr, M, st));
@@ -569,7 +596,7 @@ int make_tables_and_green(fm_plan_s* p, hipStream_t st, bool deferred) {
     if (!p->stw.count(M)) {
       void* ptr = nullptr;
       const size_t n = (size_t)std::max(1, fm::stage_table_size(M, fm::max_radix((int)sizeof(T))));
-      if (hipMalloc(&ptr, sizeof(T) * 2 * n) != hipSuccess) return FM_E_NOMEM;
+      if (plan_malloc(&ptr, sizeof(T) * 2 * n) != hipSuccess) return FM_E_NOMEM;
       p->stw[M] = ptr;
       p->table_bytes += sizeof(T) * 2 * n;
       FM_HIP(fm::launch_stage_twiddles<T>(ptr, M, st));
@@ -587,7 +614,7 @@ int make_tables_and_green(fm_plan_s* p, hipStream_t st, bool deferred) {
       if (!p->wtw.count(key)) {
         void* ptr = nullptr;
         const size_t n = (size_t)std::max(1, fm::wave_tw_size(M, E));
-        if (hipMalloc(&ptr, sizeof(T) * 2 * n) != hipSuccess) return FM_E_NOMEM;
+        if (plan_malloc(&ptr, sizeof(T) * 2 * n) != hipSuccess) return FM_E_NOMEM;
         p->wtw[key] = ptr;
         p->table_bytes += sizeof(T) * 2 * n;
         FM_HIP(fm::launch_wave_twiddles<T>(ptr, M, E, st));
@@ -627,7 +654,7 @@ int make_tables_and_green(fm_plan_s* p, hipStream_t st, bool deferred) {
       }
     }
     void* ptr = nullptr;
-    if (hipMalloc(&ptr, sizeof(T) * host.size()) != hipSuccess) return FM_E_NOMEM;
+    if (plan_malloc(&ptr, sizeof(T) * host.size()) != hipSuccess) return FM_E_NOMEM;
     p->dtab = ptr;
     p->table_bytes += sizeof(T) * host.size();
     FM_HIP(hipMemcpy(ptr, host.data(), sizeof(T) * host.size(), hipMemcpyHostToDevice));
@@ -672,7 +699,7 @@ int make_tables_and_green(fm_plan_s* p, hipStream_t st, bool deferred) {
   }
   const int64_t ns = (int64_t)Fs[0] * Fs[1] * Fs[2];
   double* S = nullptr;
-  if (hipMalloc(&S, sizeof(double) * ns) != hipSuccess) return FM_E_NOMEM;
+  if (plan_malloc(&S, sizeof(double) * ns) != hipSuccess) return FM_E_NOMEM;
   p->gen_free.push_back(S);
   int rc = FM_OK;
   if (p->green == FM_GREEN_LGF2 && du == 3) {
@@ -695,9 +722,9 @@ int make_tables_and_green(fm_plan_s* p, hipStream_t st, bool deferred) {
     lg.K = (int)std::ceil((u_hi - lg.u_lo) / lg.du) + 1;
     double* A = nullptr;
     double* W = nullptr;
-    if (hipMalloc(&A, sizeof(double) * 3 * (size_t)lg.K * lg.stride) != hipSuccess) return FM_E_NOMEM;
+    if (plan_malloc(&A, sizeof(double) * 3 * (size_t)lg.K * lg.stride) != hipSuccess) return FM_E_NOMEM;
     p->gen_free.push_back(A);
-    if (hipMalloc(&W, sizeof(double) * 2 * (size_t)lg.K) != hipSuccess) return FM_E_NOMEM;
+    if (plan_malloc(&W, sizeof(double) * 2 * (size_t)lg.K) != hipSuccess) return FM_E_NOMEM;
     p->gen_free.push_back(W);
     FM_HIP(fm::launch_lgf(S, A, W, lg, st));
   } else {
@@ -707,7 +734,7 @@ int make_tables_and_green(fm_plan_s* p, hipStream_t st, bool deferred) {
   p->gen_desc.assign(3, fm::PassDesc{});  // host copies stay alive until the copies ran
   fm::PassDesc* gdesc = p->gen_desc.data();
   fm::PassDesc* gdev = nullptr;
-  if (hipMalloc(&gdev, sizeof(fm::PassDesc) * 3) != hipSuccess) return FM_E_NOMEM;
+  if (plan_malloc(&gdev, sizeof(fm::PassDesc) * 3) != hipSuccess) return FM_E_NOMEM;
   p->gen_free.push_back(gdev);
   for (int i = 0; i < 3 && rc == FM_OK; ++i) {
     if (!g.unb[i]) continue;
@@ -743,7 +770,7 @@ int make_tables_and_green(fm_plan_s* p, hipStream_t st, bool deferred) {
     void* t64 = nullptr;
     auto it = p->tw64.find(d.M);
     if (it == p->tw64.end()) {
-      if (hipMalloc(&t64, sizeof(double) * 2 * 4 * (size_t)d.M) != hipSuccess) { rc = FM_E_NOMEM; break; }
+      if (plan_malloc(&t64, sizeof(double) * 2 * 4 * (size_t)d.M) != hipSuccess) { rc = FM_E_NOMEM; break; }
       p->tw64[d.M] = t64;
       FM_HIP(fm::launch_twiddles<double>(t64, d.M, st));
     } else {
@@ -757,7 +784,7 @@ int make_tables_and_green(fm_plan_s* p, hipStream_t st, bool deferred) {
   }
   if (rc == FM_OK) {
     const int64_t nG = (int64_t)F[0] * F[1] * F[2];
-    if (hipMalloc(&p->G, sizeof(T) * nG) != hipSuccess) {
+    if (plan_malloc(&p->G, sizeof(T) * nG) != hipSuccess) {
       rc = FM_E_NOMEM;
     } else {
       p->table_bytes += sizeof(T) * nG;
@@ -768,7 +795,7 @@ int make_tables_and_green(fm_plan_s* p, hipStream_t st, bool deferred) {
   for (int i = 0; i < fm_plan_s::kPasses; ++i) p->pass[i].g.G = p->G;
   if (rc == FM_OK) {
     const size_t nb = sizeof(fm::PassDesc) * fm_plan_s::kPasses;
-    if (hipMalloc(&p->dpass, nb) != hipSuccess) rc = FM_E_NOMEM;
+    if (plan_malloc(&p->dpass, nb) != hipSuccess) rc = FM_E_NOMEM;
     else p->table_bytes += nb;
     if (rc == FM_OK) FM_HIP(hipMemcpyAsync(p->dpass, p->pass, nb, hipMemcpyHostToDevice, st));
   }
@@ -808,7 +835,7 @@ void free_plan(fm_plan_s* p) {
 // host threads solving with one plan allocate it once); nullptr if allocation fails.
 char* own_workspace(fm_plan_s* p) {
   std::lock_guard<std::mutex> lock(p->ws_mu);
-  if (!p->ws_internal && hipMalloc(&p->ws_internal, p->ws_bytes) != hipSuccess) {
+  if (!p->ws_internal && plan_malloc(&p->ws_internal, p->ws_bytes) != hipSuccess) {
     p->ws_internal = nullptr;
     return nullptr;
   }
@@ -1881,8 +1908,8 @@ int fm_plan_tune(fm_plan p, void* workspace_dev, void* hip_stream) {
   const size_t ubytes = (size_t)p->Vu * p->ncomp * p->elem;
   void* rhs = nullptr;
   void* out = nullptr;
-  if (hipMalloc(&rhs, ubytes) != hipSuccess) return FM_E_NOMEM;
-  if (hipMalloc(&out, ubytes) != hipSuccess) {
+  if (plan_malloc(&rhs, ubytes) != hipSuccess) return FM_E_NOMEM;
+  if (plan_malloc(&out, ubytes) != hipSuccess) {
     (void)hipFree(rhs);
     return FM_E_NOMEM;
   }
