@@ -32,7 +32,7 @@ template <int KIND, int E>
 static hipError_t launch_wave_e(const PassDesc& d, const PassDesc* dev, const void* in, void* out,
                                 hipStream_t st) {
   if constexpr (wave_length(FM_MC, E) &&
-                (KIND == K_F_C2C || (KIND == K_F_CURL && (sizeof(FM_T) == 4 || E == 8)))) {
+                (KIND == K_F_C2C || (KIND == K_F_CURL && (sizeof(FM_T) == 4 || E == 8 || FM_MC == 1024)))) {
     const int threads = 64 * (d.B / wave_lines(FM_MC, E));
     if (threads < 64 || threads > kThreads) return hipErrorInvalidValue;
     if (d.lds_bytes > kSoftLds) {

@@ -251,6 +251,8 @@ struct fm_plan_s {
   // backward (spectrum -> B) transforms of fm_fft_forward / fm_fft_backward
   static constexpr int kPasses = 7;
   fm::PassDesc pass[kPasses];
+  bool long_rt[kPasses] = {};  // the pass needs the runtime-length class in the LDS-tile kernel
+  const void* stw_plan[kPasses] = {};  // stage table of the planned kernel (null: runtime-length class)
   int ext_spec[3];
   int64_t Vspec;
   bool cplx_spec;
@@ -421,7 +423,7 @@ int choose_tile(fm::PassDesc* d, size_t elem, int comps, bool fused_r2r, int nb,
 // The per-wavefront fused kernel (fm_wave.h) with E values per lane: complex fused
 // passes of a power-of-two length whose lines are contiguous in memory (every fused
 // complex pass: the last axis is the fastest of its layout); three-component lines of 16
-// values per lane in FP32 only.
+// values per lane in FP64 only at 1024 points (one line per wavefront).
 int wave_plain_rs(const fm::PassDesc& d, int E);
 
 bool wave_capable(const fm::PassDesc& d, size_t elem, int E) {
@@ -429,7 +431,7 @@ bool wave_capable(const fm::PassDesc& d, size_t elem, int E) {
   if (d.long_rt || !fm::wave_length(d.M, E) || !fm::is_fast_len(d.M)) return false;
   if (!d.fused) return wave_plain_rs(d, E) > 0;
   if (d.gather != fm::G_CPLX) return false;
-  if (d.g.curl && elem != 4 && E == 16) return false;
+  if (d.g.curl && elem != 4 && E == 16 && d.M != 1024) return false;
   return d.in_s_line == 1 && d.out_s_line == 1;
 }
 
@@ -588,10 +590,16 @@ int make_tables_and_green(fm_plan_s* p, hipStream_t st, bool deferred) {
     FM_HIP(fm::launch_twiddles<T>(ptr, M, st));
   }
   for (int i = 0; i < fm_plan_s::kPasses; ++i) p->pass[i].tw = p->tw[p->pass[i].M];
-  // per-stage tables of the lengths with compile-time kernels
+  // per-stage tables of the lengths with compile-time kernels; also of a pass planned in
+  // the runtime-length class that the tuner may move to the per-wavefront kernel (the
+  // table selects the compile-time class at launch, fm_plan_s::stw_plan keeps the planned
+  // choice)
   for (int i = 0; i < fm_plan_s::kPasses; ++i) {
     const int M = p->pass[i].M;
-    if (!compile_time_kernel(p->pass[i], p->elem)) continue;
+    fm::PassDesc c = p->pass[i];
+    c.long_rt = 0;
+    const bool planned = compile_time_kernel(p->pass[i], p->elem);
+    if (!planned && !(p->long_rt[i] && wave_capable(c, p->elem))) continue;
     if (tile_in_span_bytes(p->pass[i], p->elem) >= (int64_t(1) << 32)) continue;
     if (!p->stw.count(M)) {
       void* ptr = nullptr;
@@ -601,14 +609,17 @@ int make_tables_and_green(fm_plan_s* p, hipStream_t st, bool deferred) {
       p->table_bytes += sizeof(T) * 2 * n;
       FM_HIP(fm::launch_stage_twiddles<T>(ptr, M, st));
     }
-    p->pass[i].stw = p->stw[M];
+    if (planned) p->pass[i].stw = p->stw[M];
   }
+  for (int i = 0; i < fm_plan_s::kPasses; ++i) p->stw_plan[i] = p->pass[i].stw;
 
   // stage twiddles of the per-wavefront kernels (a pass may run there, now or after
   // tuning), one table per length and values per lane
   for (int i = 0; i < 5; ++i) {
+    fm::PassDesc w = p->pass[i];
+    w.long_rt = 0;  // the per-wavefront kernels take the compile-time length class
     for (const int E : {16, 8}) {
-      if (!wave_capable(p->pass[i], p->elem, E)) continue;
+      if (!wave_capable(w, p->elem, E)) continue;
       const int M = p->pass[i].M;
       const int key = (M << 5) | E;
       if (!p->wtw.count(key)) {
@@ -1231,6 +1242,7 @@ int build_plan(fm_plan_s* p) {
     if (rc2 && p->prec == FM_F64) {
       // no tile fits 8 FP64 values per thread: the runtime-length class with 16
       d.long_rt = 1;
+      p->long_rt[i] = true;
       rc2 = choose_tile(&d, p->elem, fused_curl ? 3 : 1, (i == 2) && d.gather == fm::G_R2R, d.nb);
     }
     if (rc2) return rc2;
@@ -1783,11 +1795,21 @@ bool retile(const fm_plan_s* p, int i, int bmax, int mode, fm::PassDesc* out) {
   const int64_t sizes_in[5] = {p->Vu, p->V1, p->V2, p->V2, p->V1};
   const int64_t sizes_out[5] = {p->V1, p->V2, p->V2, p->V1, p->Vu};
   d.wave = 0;
+  // the per-wavefront kernel has the compile-time length; the LDS-tile kernel takes the
+  // class the plan chose
+  d.long_rt = (mode == 3 || mode == 4) ? 0 : p->long_rt[i];
+  d.stw = p->stw_plan[i];
   if (mode == 3 || mode == 4) {
     // the per-wavefront kernel (16 or 8 values per lane): the most wavefronts per
-    // workgroup within bmax lines
+    // workgroup within bmax lines; launched in the compile-time class, which the stage
+    // table selects
     const int E = mode == 3 ? 16 : 8;
     if (!wave_capable(d, p->elem, E)) return false;
+    if (!d.stw) {
+      const auto t = p->stw.find(d.M);
+      if (t == p->stw.end()) return false;
+      d.stw = t->second;
+    }
     for (const int W : {4, 2, 1}) {
       fm::PassDesc w = d;
       const int lines = W * fm::wave_lines(d.M, E) * (d.fused ? 1 : wave_plain_pk(d));

@@ -122,9 +122,13 @@ __device__ __forceinline__ void wave_tile(const PassDesc& d, const void* in, voi
   const auto* G = gptr<T>(d.g.G);
   const int64_t grow = ((int64_t)fold_index(ti.c, d.g.fold_c) * d.g.F_b + fold_index(b, d.g.fold_b)) *
                        (int64_t)d.g.F_line;
+  // Poisson: the row is loaded ahead of the transforms (its latency hides behind them);
+  // the curl loads it after its three forward transforms, when registers are free
   T g[E];
+  if constexpr (KIND != K_F_CURL) {
 #pragma unroll
-  for (int m = 0; m < E; ++m) g[m] = G[grow + fold_index(j + P * m, d.g.fold_line)];
+    for (int m = 0; m < E; ++m) g[m] = G[grow + fold_index(j + P * m, d.g.fold_line)];
+  }
 
   cpx<T> v[NCL][E];
 #pragma unroll
@@ -142,6 +146,8 @@ __device__ __forceinline__ void wave_tile(const PassDesc& d, const void* in, voi
     wave_stages<T, M, E, 0, -1>(v[q], j, buf, tw);
   }
   if constexpr (KIND == K_F_CURL) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) g[m] = G[grow + fold_index(j + P * m, d.g.fold_line)];
     const T wc = curl_wave<T>(ti.c, d.g.dtab_c);
     const T wb = curl_wave<T>(b, d.g.dtab_b);
 #pragma unroll
@@ -181,12 +187,14 @@ __device__ __forceinline__ void wave_tile(const PassDesc& d, const void* in, voi
 
 // Tiles in the XCD-aware order of the other pass kernels; a grid of one workgroup per
 // tile gives each workgroup one or two tiles.
-// Occupancy targets of the three-component (curl) kernels: 16 values per lane need the
-// 256 VGPRs of two waves per SIMD; 8 FP32 values fit the 168 of three (FP64 would spill
-// there and keeps the compiler's choice).
+// Occupancy targets of the three-component (curl) kernels: 16 values per lane (1024-point
+// lines) keep one wave per SIMD, where FP32 fits without spilling (two waves spill some
+// 300 bytes per lane and ran 20 % slower on the 512^3 Biot-Savart pass) and FP64 takes the
+// 512 architectural and accumulation registers; 8 FP32 values fit the 168 of three (FP64
+// would spill there and keeps the compiler's choice).
 template <typename T, int KIND, int E>
 constexpr int wave_min_waves() {
-  return KIND == K_F_CURL ? (E == 16 ? 2 : (sizeof(T) == 4 ? 3 : 1)) : 1;
+  return KIND == K_F_CURL ? (E == 16 ? 1 : (sizeof(T) == 4 ? 3 : 1)) : 1;
 }
 
 template <typename T, int M, int KIND, int E>

@@ -91,9 +91,8 @@ def test_biot_savart_1024_lines_against_oracle(long_axis, prec, tol):
     """The kernels of the 512^3 Biot-Savart solve, against the oracle: one axis of 512
     cells (FFT length 1024, as every axis at 512^3) and two short ones.  The passes along
     the long axis run in the launch mode the tuner picks at 512^3, with as many lines per
-    tile as the short axes allow; along z this is the fused curl pass (in FP64 the long
-    runtime-length class, as at 512^3), along x the first and last passes, along y the
-    second and fourth."""
+    tile as the short axes allow; along z this is the fused curl pass, along x the first
+    and last passes, along y the second and fourth."""
     n = [6, 6, 6]
     n[long_axis] = 512
     h = [2 / 512] * 3
