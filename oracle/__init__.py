@@ -65,6 +65,7 @@ def lib():
         L.oracle_green_value.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.oracle_green_value.restype = ctypes.c_double
         L.oracle_solve.argtypes = [ip, dp, ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp]
+        L.oracle_solve_vector.argtypes = [ip, dp, ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp]
         L.oracle_green_spectrum.argtypes = [ip, dp, ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
         L.oracle_spectral_dims.argtypes = [ip, dp, ip, ctypes.c_int, ip]
         L.oracle_direct_points.argtypes = [ip, dp, ip, ctypes.c_int, ctypes.c_int, dp, ctypes.c_int, ip, dp]
@@ -176,6 +177,33 @@ def solve(rhs, n, h, bc, layout, green=0, kind=0, mode=FAST):
     _prepare_lgf(n, h, bc, green)
     _check(lib().oracle_solve(_ip(n), _dp(h), _ip(bc), layout, green, kind, mode, _dp(rhs), _dp(out)))
     return out if kind >= 1 else out[0]
+
+
+def swap_faces(bcv):
+    """The faces of the velocity for source faces bcv [3][3][2]: even and odd swapped."""
+    sw = {EVEN: ODD, ODD: EVEN, PER: PER, UNB: UNB}
+    return [[[sw[int(f)] for f in ax] for ax in comp] for comp in np.asarray(bcv).tolist()]
+
+
+def solve_vector(rhs, n, h, bcv, layout, green=0, kind=1, mode=FAST):
+    """Biot-Savart lap(u) = curl(f) with boundary conditions per component (Sec. V).
+
+    bcv: [3][3][2], per component (x, y, z) the [[xl, xr], [yl, yr], [zl, zr]] faces.
+    Periodic and unbounded faces are shared by the components; on a symmetric face of
+    axis a the component along a has one symmetry and the two others the opposite one.
+    Component p of the result has the faces of component p with even and odd swapped
+    (swap_faces).  kind 1 spectral derivative, 2 / 3 / 4 finite differences.
+    rhs: [3, nz, ny, nx] FP64."""
+    n = np.ascontiguousarray(n, dtype=np.int32)
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    b = np.ascontiguousarray(np.asarray(bcv).reshape(-1), dtype=np.int32)
+    assert n.size == 3 and h.size == 3 and b.size == 18
+    shp = user_shape(n, layout)
+    rhs = np.ascontiguousarray(rhs, dtype=np.float64).reshape((3,) + shp)
+    out = np.empty_like(rhs)
+    _prepare_lgf(n, h, b[:6], green)
+    _check(lib().oracle_solve_vector(_ip(n), _dp(h), _ip(b), layout, green, kind, mode, _dp(rhs), _dp(out)))
+    return out
 
 
 def direct_points(rhs, n, h, bc, layout, points, green=0):

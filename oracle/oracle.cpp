@@ -353,8 +353,9 @@ int make_axis(int N, double h, int node, int bl, int br, Axis* a) {
   return 0;
 }
 
-// Wavenumber of spectral mode s on a spectral axis (periodic or symmetric), or of the
-// doubled-domain DFT mode s on a fully unbounded axis (used by the curl).  The Nyquist
+// Wavenumber of spectral mode s on a spectral axis (periodic or symmetric), of the
+// doubled-domain DFT mode s on a fully unbounded axis, or of the DCT / DST mode s on the
+// 2L extension of a semi-unbounded axis (the last two used by the curl).  The Nyquist
 // mode of an even-length DFT gets 0 when `nyquist_zero` is set.
 double omega(const Axis& a, int s, bool nyquist_zero) {
   if (a.dft) {
@@ -364,7 +365,7 @@ double omega(const Axis& a, int s, bool nyquist_zero) {
     const int k = (2 * s > n) ? s - n : s;
     return 2.0 * kPi * k / period;
   }
-  return kPi * (s + a.kshift + a.half) / a.L();
+  return kPi * (s + a.kshift + a.half) / (a.unb ? 2.0 * a.L() : a.L());
 }
 
 // Forward operation along one axis: user line (nuser) -> spectral line (nspec).
@@ -820,6 +821,101 @@ int solve_spectral(const Problem& P, const double* rhs, double* out, int mode) {
   return 0;
 }
 
+// Biot-Savart with boundary conditions per component (Sec. V).  A derivative along a
+// symmetric direction turns an even field odd and an odd one even, so component p of the
+// velocity takes, face by face, the opposite symmetry of component p of the source, and
+// its backward transform is the swapped DCT / DST.  Periodic and unbounded faces are
+// shared by the three components; on a symmetric face of axis a the component along a
+// has one symmetry and the two others the opposite one (the faces of a mirror-symmetric
+// vector field), otherwise the problem is rejected (-1).
+// bcv[18] = per component q (x, y, z), per axis a, (left, right): bcv[6 q + 2 a + f].
+int swap_face(int b) { return b == BC_EVEN ? BC_ODD : (b == BC_ODD ? BC_EVEN : b); }
+
+int vector_faces_ok(const int* bcv) {
+  for (int a = 0; a < 3; ++a)
+    for (int f = 0; f < 2; ++f) {
+      const int t[3] = {bcv[2 * a + f], bcv[6 + 2 * a + f], bcv[12 + 2 * a + f]};
+      const bool sym = t[0] <= BC_ODD || t[1] <= BC_ODD || t[2] <= BC_ODD;
+      if (!sym) {
+        if (t[0] != t[1] || t[0] != t[2]) return -1;
+        continue;
+      }
+      const int b = (a + 1) % 3, c = (a + 2) % 3;  // the two tangential components
+      if (t[a] > BC_ODD || t[b] > BC_ODD || t[c] > BC_ODD) return -1;
+      if (t[b] != t[c] || t[a] == t[b]) return -1;
+    }
+  return 0;
+}
+
+// Each component is transformed with its own conditions and multiplied by the Green's
+// spectrum in its own indexing (psi_hat_b = G_hat f_hat_b).  Coefficients of one frequency
+// index K sit at index K - kshift of every spectrum, so that u_hat_p at the index of
+// frequency K gathers the psi_hat_b of the same K.  The derivative along a periodic or
+// unbounded direction is i w (Sec. V); along a symmetric or semi-unbounded one the
+// coefficient of a sine transform stands for the complex value -i times it, so the
+// derivative is +w times it, and a cosine coefficient's derivative is -w times it (that
+// value, with the sign changed for the backward sine transform); on a reversed axis (a
+// semi-unbounded one symmetric on the right) both signs flip.  The finite-difference
+// kinds replace w by their symbols.
+int solve_vector(const Problem Pin[3], const Problem Pout[3], int kind, const double* rhs,
+                 double* out, int mode) {
+  const Dims du = user_dims(Pin[0]);
+  const long V = du.size();
+  std::vector<std::vector<cd>> psi(3);
+  for (int b = 0; b < 3; ++b) {
+    std::vector<cd> f(V);
+    for (long i = 0; i < V; ++i) f[i] = rhs[b * V + i];
+    psi[b] = forward3(Pin[b], f, mode);
+    const std::vector<cd> G = green_spectrum(Pin[b], mode);
+    for (size_t i = 0; i < psi[b].size(); ++i) psi[b][i] *= G[i];
+  }
+  auto deriv = [&](const Axis& A, int s) {
+    const double w = omega(A, s, true);
+    if (kind == 1) return w;
+    const double wh = omega(A, s, false) * A.h;
+    if (kind == 2) return std::sin(wh) / A.h;
+    if (kind == 3) return (4.0 / 3.0 * std::sin(wh) - 1.0 / 6.0 * std::sin(2.0 * wh)) / A.h;
+    return (1.5 * std::sin(wh) - 0.3 * std::sin(2.0 * wh) + std::sin(3.0 * wh) / 30.0) / A.h;
+  };
+  auto is_sine = [](int k) { return k >= RODFT00; };
+  const cd I(0.0, 1.0);
+  for (int p = 0; p < 3; ++p) {
+    const Problem& Q = Pout[p];
+    const long nx = Q.ax[0].nspec, ny = Q.ax[1].nspec, nz = Q.ax[2].nspec;
+    std::vector<cd> uh(nx * ny * nz);
+    // u_p = D_a psi_b - D_b psi_a with (p, a, b) cyclic
+    const int a = (p + 1) % 3, b = (p + 2) % 3;
+    // D_e psi_c at output index s[3]
+    auto term = [&](int e, int c, const long* s) -> cd {
+      long t[3];
+      for (int x = 0; x < 3; ++x) {
+        const Axis& Ao = Q.ax[x];
+        const Axis& Ai = Pin[c].ax[x];
+        t[x] = Ao.dft ? s[x] : s[x] + Ao.kshift - Ai.kshift;
+        if (t[x] < 0 || t[x] >= Ai.nspec) return cd(0.0, 0.0);
+      }
+      const long ni0 = Pin[c].ax[0].nspec, ni1 = Pin[c].ax[1].nspec;
+      const cd v = psi[c][t[0] + ni0 * (t[1] + ni1 * t[2])];
+      const double w = deriv(Q.ax[e], (int)s[e]);
+      if (Q.ax[e].dft) return I * w * v;
+      // a symmetric face on the right: the transforms see the reversed line x' = L - x,
+      // and d/dx = -d/dx'
+      const double sg = (is_sine(Pin[c].ax[e].fwd) ? 1.0 : -1.0) * (Q.ax[e].rev ? -1.0 : 1.0);
+      return sg * w * v;
+    };
+#pragma omp parallel for collapse(2) schedule(static)
+    for (long z = 0; z < nz; ++z)
+      for (long y = 0; y < ny; ++y)
+        for (long x = 0; x < nx; ++x) {
+          const long s[3] = {x, y, z};
+          uh[x + nx * (y + ny * z)] = term(a, b, s) - term(b, a, s);
+        }
+    const std::vector<cd> u = backward3(Q, uh, mode);
+    for (long i = 0; i < V; ++i) out[p * V + i] = u[i].real();
+  }
+  return 0;
+}
+
 // Direct form: spectral directions by their defining sums, convolution directions as an
 // explicit sum over the user's points and their images (even image: same sign, odd
 // image: opposite sign; a node on the symmetric face is its own image and counts once).
@@ -1100,6 +1196,26 @@ int oracle_solve(const int* n, const double* h, const int* bc, int layout, int g
   if (rc) return rc;
   if (mode == MODE_DIRECT) return solve_direct(P, rhs, out);
   return solve_spectral(P, rhs, out, mode == MODE_NAIVE ? MODE_NAIVE : MODE_FAST);
+}
+
+// Biot-Savart with boundary conditions per component: bcv[18] = (component q, axis a,
+// face f) at 6 q + 2 a + f, codes as for oracle_solve; kind 1 spectral curl, 2 / 3 / 4
+// finite differences of order 2 / 4 / 6; mode 0 fast / 1 naive.  rhs, out: [3][nz][ny][nx].
+// Component p of the result satisfies the swapped symmetry of component p of bcv.
+int oracle_solve_vector(const int* n, const double* h, const int* bcv, int layout, int green,
+                        int kind, int mode, const double* rhs, double* out) {
+  if (kind < 1 || kind > 4) return -3;
+  if (vector_faces_ok(bcv)) return -1;
+  Problem Pin[3], Pout[3];
+  for (int q = 0; q < 3; ++q) {
+    int swapped[6];
+    for (int i = 0; i < 6; ++i) swapped[i] = swap_face(bcv[6 * q + i]);
+    int rc = make_problem(n, h, bcv + 6 * q, layout, green, 0, &Pin[q]);
+    if (rc) return rc;
+    rc = make_problem(n, h, swapped, layout, green, 0, &Pout[q]);
+    if (rc) return rc;
+  }
+  return solve_vector(Pin, Pout, kind, rhs, out, mode == MODE_NAIVE ? MODE_NAIVE : MODE_FAST);
 }
 
 // The solution at npts user points (x, y, z indices in pts[3 * npts]) by the direct
