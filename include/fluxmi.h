@@ -100,8 +100,9 @@ typedef enum {
 #define FM_E_BC (-2)     /* periodic on one face only, or an unknown code             */
 #define FM_E_SIZE (-3)   /* N < 2, h <= 0, or an FFT length with a prime factor > 7
                             or longer than 4096                                       */
-#define FM_E_KIND (-4)   /* unknown kind / green / precision / layout, or Biot-Savart
-                            with ncomp != 3 or a symmetric / semi-unbounded axis      */
+#define FM_E_KIND (-4)   /* unknown kind / green / precision / layout, Biot-Savart with
+                            ncomp != 3, or with a symmetric / semi-unbounded axis in
+                            fm_plan_create (fm_plan_create_vector takes one)          */
 #define FM_E_NOMEM (-5)  /* device allocation failed                                 */
 #define FM_E_HIP (-6)    /* a HIP call failed; fm_last_hip_error() has its code      */
 #define FM_E_ARG (-7)    /* inconsistent arguments (count, workspace too small, ...) */
@@ -126,6 +127,25 @@ typedef struct fm_plan_s* fm_plan;
  * The plan owns its device memory (spectrum, twiddles, internal workspace). */
 int fm_plan_create(fm_plan* out, const int n[3], const double h[3], const int bc[3][2],
                    int layout, int green, int prec, int kind, int ncomp, void* hip_stream);
+
+/* Biot-Savart with boundary conditions per component (Sec. V): lap(u) = curl(f) for a
+ * source f whose components have their own faces, bc[q][a][f] for component q (x, y, z),
+ * axis a, face f (left, right).  The faces must be those of a mirror-symmetric vector
+ * field: periodic and unbounded faces are shared by the three components; on a symmetric
+ * (even or odd) face of axis a, component a has one symmetry and the two other
+ * components the opposite one (else FM_E_BC).  A derivative along a symmetric direction
+ * turns even into odd and odd into even, so component p of the solution has the faces of
+ * component p of f with even and odd swapped; in spectral space the derivative of a sine
+ * coefficient is +w times it and that of a cosine coefficient -w times it (Sec. V).
+ * One axis may be symmetric or semi-unbounded (Sec. II-B, II-C), the two others periodic
+ * or unbounded (else FM_E_KIND); without a symmetric face the plan is fm_plan_create's
+ * Biot-Savart plan.  kind: FM_BIOT_SAVART or one of its _FD forms; the other arguments,
+ * the ownership and the solve calls as for fm_plan_create with ncomp = 3.  Such a plan
+ * is solved one request at a time: fm_solve_batched, fm_batch_prepare, fm_fft_forward
+ * and fm_fft_backward return FM_E_KIND for it.
+ * Errors: FM_E_NULL, FM_E_BC, FM_E_SIZE, FM_E_KIND, FM_E_NOMEM, FM_E_HIP. */
+int fm_plan_create_vector(fm_plan* out, const int n[3], const double h[3], const int bc[3][3][2],
+                          int layout, int green, int prec, int kind, void* hip_stream);
 
 /* Release a plan and its device memory.  The caller must make sure no solve that
  * uses it is still in flight.  NULL is accepted and ignored. */

@@ -683,6 +683,46 @@ __device__ __forceinline__ T signed_wave(int k, int M, T dw) {
   return dw * T(ks);
 }
 
+// u_hat = G i (w x f_hat) at one spectral point (Sec. V), in place.  The wavenumber of
+// the c direction (physical axis ac) may be imaginary, i m (a symmetric c direction,
+// GreenRef::csym; its real part wx / wy / wz is then 0): its terms i m (e_c x f) are
+// added under a branch that is uniform across the wavefront.
+template <typename T>
+__device__ __forceinline__ void curl_point(T g, T wx, T wy, T wz, int ac, T m, cpx<T>& fx, cpx<T>& fy,
+                                           cpx<T>& fz) {
+  cpx<T> cx = {wy * fz.x - wz * fy.x, wy * fz.y - wz * fy.y};
+  cpx<T> cy = {wz * fx.x - wx * fz.x, wz * fx.y - wx * fz.y};
+  cpx<T> cz = {wx * fy.x - wy * fx.x, wx * fy.y - wy * fx.y};
+  if (m != T(0)) {
+    // i m (e_c x f): e_x x f = (0, -f_z, f_y), e_y x f = (f_z, 0, -f_x), e_z x f = (-f_y, f_x, 0)
+    auto add = [m](cpx<T>& c, const cpx<T>& f, T sg) {  // c += sg i m f
+      c.x -= sg * m * f.y;
+      c.y += sg * m * f.x;
+    };
+    if (ac == 0) {
+      add(cy, fz, T(-1));
+      add(cz, fy, T(1));
+    } else if (ac == 1) {
+      add(cx, fz, T(1));
+      add(cz, fx, T(-1));
+    } else {
+      add(cx, fy, T(-1));
+      add(cy, fx, T(1));
+    }
+  }
+  fx = {-g * cx.y, g * cx.x};
+  fy = {-g * cy.y, g * cy.x};
+  fz = {-g * cz.y, g * cz.x};
+}
+
+// The c-direction factor of the curl: (real, imaginary) = (w, 0) on a DFT direction,
+// (0, -s w) on a symmetric or semi-unbounded one (GreenRef::csym = s).
+template <typename T>
+__device__ __forceinline__ void curl_c_factor(const GreenRef& gr, T w, T& re, T& im) {
+  re = gr.csym ? T(0) : w;
+  im = gr.csym ? T(-gr.csym) * w : T(0);
+}
+
 // Derivative factor of DFT mode k in the curl, from the direction's table: the spectral
 // wavenumber (0 at the Nyquist mode) or the plan's central-difference symbol (Sec. V).
 template <typename T>
@@ -974,7 +1014,8 @@ __device__ void fused_compute(const PassDesc& d, void* out, const TileIdx& ti, c
     }
     fft_lines<T, MC, +1>(buf, ls, F, d, tb.stw, lds_g, min(d.out_n, M));
   } else {
-    const T wc = curl_wave<T>(c, d.g.dtab_c);
+    T wc, mc;
+    curl_c_factor<T>(d.g, curl_wave<T>(c, d.g.dtab_c), wc, mc);
     struct Tri {
       cpx<T> x, y, z;
     };
@@ -988,14 +1029,11 @@ __device__ void fused_compute(const PassDesc& d, void* out, const TileIdx& ti, c
           const T wx = d.g.axis_line == 0 ? wl : (d.g.axis_b == 0 ? wb : wc);
           const T wy = d.g.axis_line == 1 ? wl : (d.g.axis_b == 1 ? wb : wc);
           const T wz = d.g.axis_line == 2 ? wl : (d.g.axis_b == 2 ? wb : wc);
-          const cpx<T> fx = buf[(0 * nl + l) * ls + pad16(k)];
-          const cpx<T> fy = buf[(1 * nl + l) * ls + pad16(k)];
-          const cpx<T> fz = buf[(2 * nl + l) * ls + pad16(k)];
-          // u_hat = G * i (w x f_hat)
-          const cpx<T> cx = {wy * fz.x - wz * fy.x, wy * fz.y - wz * fy.y};
-          const cpx<T> cy = {wz * fx.x - wx * fz.x, wz * fx.y - wx * fz.y};
-          const cpx<T> cz = {wx * fy.x - wy * fx.x, wx * fy.y - wy * fx.y};
-          return Tri{{-g * cx.y, g * cx.x}, {-g * cy.y, g * cy.x}, {-g * cz.y, g * cz.x}};
+          cpx<T> fx = buf[(0 * nl + l) * ls + pad16(k)];
+          cpx<T> fy = buf[(1 * nl + l) * ls + pad16(k)];
+          cpx<T> fz = buf[(2 * nl + l) * ls + pad16(k)];
+          curl_point<T>(g, wx, wy, wz, d.g.axis_c, mc, fx, fy, fz);
+          return Tri{fx, fy, fz};
         },
         [&](int e, const Tri& v) {
           const int l = e / M, k = e - l * M;

@@ -108,7 +108,15 @@ struct GreenRef {
   const void* dtab_line;
   const void* dtab_b;
   const void* dtab_c;
+  // a symmetric or semi-unbounded c direction (conditions per component, Sec. V): the
+  // derivative of a component along it is s w times its real-to-real coefficient, s = +1
+  // after a sine transform and -1 after a cosine one (both flipped on a reversed axis).
+  // The kernels form u_hat = G i (w x f_hat); only the two components tangential to c
+  // (which share their faces, hence s) enter its c-direction terms, so the c factor
+  // becomes the complex -i s w.  csym = s, or 0 when c is a DFT direction.
+  int32_t csym;
 };
+
 
 // Output conventions applied by the last pass along its two batch axes (Sec. II-A,
 // II-B): node-centred periodic duplicate f_N := f_0, nodes on odd faces := 0.

@@ -173,7 +173,9 @@ int plan_axis(int N, double h, bool node, int bl, int br, AxisPlan* a) {
 // R2R descriptor of kind `k` with n points, mapped onto the line arrays.
 //  forward (dir = +1): input = user line (nuser, `first`, reversal), output = spectrum
 //  backward (dir = -1): input = spectrum, output = user line
-fm::R2R make_r2r(const AxisPlan& a, int kind, bool forward) {
+// common: spectral index = frequency index (the spectra of several components, of
+// different kinds, share one indexing; the slots outside a kind's range hold 0).
+fm::R2R make_r2r(const AxisPlan& a, int kind, bool forward, bool common = false) {
   const KindForm f = kind_form(kind);
   const int n = a.nin;
   fm::R2R r{};
@@ -192,10 +194,10 @@ fm::R2R make_r2r(const AxisPlan& a, int kind, bool forward) {
     if (a.rev) { r.in_rev = 1; r.in_base = a.nuser - 1 - a.first + f.pin; }
     else { r.in_rev = 0; r.in_base = f.pin - a.first; }
     r.out_rev = 0;
-    r.out_base = f.qout;  // q = s + qout
+    r.out_base = common ? 0 : f.qout;  // q = s + qout
   } else {
     r.in_rev = 0;
-    r.in_base = f.pin;    // p = s + pin
+    r.in_base = common ? 0 : f.pin;    // p = s + pin
     // q = (rev ? nuser-1-j : j) - first + qout
     if (a.rev) { r.out_rev = 1; r.out_base = a.nuser - 1 - a.first + f.qout; }
     else { r.out_rev = 0; r.out_base = f.qout - a.first; }
@@ -275,6 +277,17 @@ struct fm_plan_s {
   std::vector<fm::PassDesc> gen_desc;
   int device = 0;
   size_t table_bytes = 0;  // device memory of the plan's tables (Green, twiddles, descriptors)
+  // fm_plan_create_vector: faces per component (bc above holds component 0's).  The one
+  // symmetric or semi-unbounded axis is the first transformed (a0); passes 1 and 5 run
+  // once per component, each with its own real-to-real transform (the input's kind
+  // forward, the swapped kind of the output backward), on a spectrum indexed by
+  // frequency shared by the three components.  Device descriptors of components 1 and 2
+  // follow the kPasses at dpass[kPasses + vec_slot(pass, comp)].
+  bool vec = false;
+  int bcv[3][3][2] = {};
+  fm::R2R vr2r[3][2] = {};  // [component][0: pass 1 forward, 1: pass 5 backward]
+  static constexpr int kVecDesc = 4;
+  fm::PassDesc vdesc[kVecDesc];  // host copies of the device slots (vec_slot)
 };
 
 namespace {
@@ -573,6 +586,24 @@ void release_generation(fm_plan_s* p) {
   p->tw64.clear();
 }
 
+// Device slot, after the kPasses, of component q (1 or 2) of pass i (0 or 4) of a vector
+// plan.
+int vec_slot(int i, int q) { return (i == 0 ? 0 : 2) + (q - 1); }
+
+// The descriptors of components 1 and 2 of passes 1 and 5 of a vector plan, rebuilt from
+// the plan's (component 0) descriptors with their own transforms, and uploaded.
+hipError_t upload_vec_descs(fm_plan_s* p, hipStream_t st) {
+  for (const int i : {0, 4})
+    for (int q = 1; q < 3; ++q) {
+      fm::PassDesc& d = p->vdesc[vec_slot(i, q)];
+      d = p->pass[i];
+      d.r2r = p->vr2r[q][i == 0 ? 0 : 1];
+    }
+  const hipError_t e = hipMemcpyAsync(p->dpass + fm_plan_s::kPasses, p->vdesc, sizeof(p->vdesc),
+                                      hipMemcpyHostToDevice, st);
+  return e == hipSuccess ? hipStreamSynchronize(st) : e;
+}
+
 // Twiddle tables and the Green's spectrum of a plan, generated on stream st.  With
 // deferred = false the call waits for the generation and releases its temporaries; with
 // deferred = true it records p->ready after the generation instead and leaves the
@@ -649,6 +680,27 @@ int make_tables_and_green(fm_plan_s* p, hipStream_t st, bool deferred) {
       offs[t] = host.size();
       const double ih = 1.0 / p->ax[axes[t]].h;
       const int M = Ms[t];
+      const AxisPlan& A = p->ax[axes[t]];
+      if (!A.dft) {
+        // the swap axis of a vector plan (direction c): frequency index s (+ 1/2 for the
+        // half-frequency kinds) on the period 2 nh of its transform (nh = N, or 2N on the
+        // 2L extension of a semi-unbounded axis): w = pi (2 s + b2) / (2 nh h)
+        const int b2 = kind_form(A.fwd).b2;
+        const long long nh = A.unb ? 2LL * A.N : (long long)A.N;
+        for (int k = 0; k < A.nspec; ++k) {
+          auto sn = [&](int j) {  // sin(j w h), the angle reduced exactly
+            const long long num = ((long long)j * (2LL * k + b2)) % (4LL * nh);
+            return std::sin(M_PI * (double)num / (2.0 * (double)nh));
+          };
+          double v;
+          if (order == 0) v = M_PI * (2.0 * k + b2) / (2.0 * (double)nh * A.h);
+          else if (order == 2) v = ih * sn(1);
+          else if (order == 4) v = ih * (4.0 / 3.0 * sn(1) - 1.0 / 6.0 * sn(2));
+          else v = ih * (1.5 * sn(1) - 0.3 * sn(2) + sn(3) / 30.0);
+          host.push_back(T(v));
+        }
+        continue;
+      }
       for (int k = 0; k < M; ++k) {
         const long long ks = (2 * k > M) ? k - M : k;
         auto sn = [&](int j) {  // sin(2 pi j ks / M), the angle reduced exactly
@@ -806,9 +858,11 @@ int make_tables_and_green(fm_plan_s* p, hipStream_t st, bool deferred) {
   for (int i = 0; i < fm_plan_s::kPasses; ++i) p->pass[i].g.G = p->G;
   if (rc == FM_OK) {
     const size_t nb = sizeof(fm::PassDesc) * fm_plan_s::kPasses;
-    if (plan_malloc(&p->dpass, nb) != hipSuccess) rc = FM_E_NOMEM;
-    else p->table_bytes += nb;
+    const size_t nv = p->vec ? sizeof(fm::PassDesc) * fm_plan_s::kVecDesc : 0;
+    if (plan_malloc(&p->dpass, nb + nv) != hipSuccess) rc = FM_E_NOMEM;
+    else p->table_bytes += nb + nv;
     if (rc == FM_OK) FM_HIP(hipMemcpyAsync(p->dpass, p->pass, nb, hipMemcpyHostToDevice, st));
+    if (rc == FM_OK && p->vec) FM_HIP(upload_vec_descs(p, st));
   }
   for (int i = 0; i < 3; ++i) p->GF[i] = F[i];
   if (deferred && rc == FM_OK) {
@@ -1010,10 +1064,40 @@ int build_plan(fm_plan_s* p) {
     const int nu = (int)p->ax[0].unb + (int)p->ax[1].unb + (int)p->ax[2].unb;
     if (nu != 0 && nu != 3) return FM_E_KIND;
   }
+  // conditions per component (fm_plan_create_vector): the transforms of every component,
+  // of the source (vin) and of the velocity (vout, even and odd faces swapped)
+  AxisPlan vin[3][3], vout[3][3];
+  int swap_axis = -1;
+  if (p->vec) {
+    auto sw = [](int b) { return b == FM_BC_EVEN ? FM_BC_ODD : (b == FM_BC_ODD ? FM_BC_EVEN : b); };
+    for (int q = 0; q < 3; ++q)
+      for (int a = 0; a < 3; ++a) {
+        int rc = plan_axis(p->n[a], p->h[a], node, p->bcv[q][a][0], p->bcv[q][a][1], &vin[q][a]);
+        if (rc) return rc;
+        rc = plan_axis(p->n[a], p->h[a], node, sw(p->bcv[q][a][0]), sw(p->bcv[q][a][1]), &vout[q][a]);
+        if (rc) return rc;
+      }
+    // one symmetric or semi-unbounded axis; the two others periodic or unbounded
+    for (int a = 0; a < 3; ++a)
+      if (!p->ax[a].dft) {
+        if (swap_axis >= 0) return FM_E_KIND;
+        swap_axis = a;
+      }
+    if (swap_axis < 0) return FM_E_KIND;
+    // spectral extent along it: every frequency index of the components' kinds
+    int ns = 0;
+    for (int q = 0; q < 3; ++q) {
+      const AxisPlan& ai = vin[q][swap_axis];
+      const AxisPlan& ao = vout[q][swap_axis];
+      ns = std::max(ns, kind_form(ai.fwd).qout + ai.nin);
+      ns = std::max(ns, kind_form(ao.bwd).pin + ao.nin);
+    }
+    p->ax[swap_axis].nspec = ns;
+  }
   if (p->kind != FM_POISSON) {
     if (p->ncomp != 3) return FM_E_KIND;
     for (int a = 0; a < 3; ++a)
-      if (!p->ax[a].dft) return FM_E_KIND;
+      if (!p->ax[a].dft && a != swap_axis) return FM_E_KIND;
   }
   // transform order: symmetric < semi-unbounded < periodic < unbounded (cost)
   auto cost = [](int c) {
@@ -1051,6 +1135,11 @@ int build_plan(fm_plan_s* p) {
       a.Fs = 2 * a.N + 1;  // kernel on [0, 2L]
       a.off = f.qout;      // spectral index s pairs with kernel mode s + qout
     }
+  }
+  if (swap_axis >= 0) {  // frequency-indexed spectrum along the swap axis
+    AxisPlan& a = p->ax[swap_axis];
+    if (a.unb) a.off = 0;
+    else a.shift = 0.5 * kind_form(a.fwd).b2;
   }
   const int a0 = ord[0], a1 = ord[1], a2 = ord[2];
   // tile axis of passes 1/5: the user's fastest axis x when the first transform does
@@ -1096,6 +1185,13 @@ int build_plan(fm_plan_s* p) {
     d.in_cplx = 0;
     d.in_n = p->ax[a0].nuser;
     d.out_n = p->ax[a0].nspec;
+    if (p->vec) {
+      for (int q = 0; q < 3; ++q) {
+        p->vr2r[q][0] = make_r2r(vin[q][a0], vin[q][a0].fwd, true, true);
+        p->vr2r[q][1] = make_r2r(vout[q][a0], vout[q][a0].bwd, false, true);
+      }
+      d.r2r = p->vr2r[0][0];
+    }
   }
   // pass 2: L1 -> L2 along a1, tiles along a2
   {
@@ -1151,6 +1247,13 @@ int build_plan(fm_plan_s* p) {
     g.M_c = p->ax[a0].M;
     g.deriv = p->kind == FM_BIOT_SAVART_FD2 ? 2 : p->kind == FM_BIOT_SAVART_FD4 ? 4
             : p->kind == FM_BIOT_SAVART_FD6 ? 6 : 0;
+    if (p->vec) {
+      // the derivative along the swap axis (a0, direction c) of a component tangential to
+      // it: +w after a sine transform, -w after a cosine one, both flipped on a reversed
+      // axis (Sec. V)
+      const AxisPlan& ai = vin[(a0 + 1) % 3][a0];
+      g.csym = ((ai.fwd >= RODFT00) != ai.rev) ? 1 : -1;
+    }
   }
   // pass 4: L2 -> L1 along a1 (inverse of pass 2)
   {
@@ -1172,6 +1275,7 @@ int build_plan(fm_plan_s* p) {
     d.out_cplx = 0;
     d.in_n = p->ax[a0].nspec;
     d.out_n = p->ax[a0].nuser;
+    if (p->vec) d.r2r = p->vr2r[0][1];
     // output conventions along the two batch axes
     auto fix_axis = [](const AxisPlan& A, int32_t* dup, int32_t* zlo, int32_t* zhi, int32_t* last) {
       *last = A.N;
@@ -1234,7 +1338,7 @@ int build_plan(fm_plan_s* p) {
     const int rc = radix_plan(p->ax[line_axis[i]].M, &d);
     if (rc) return rc;
     const bool fused_curl = (i == 2) && curl;
-    d.ncomp = p->ncomp;
+    d.ncomp = (p->vec && (i == 0 || i == 4)) ? 1 : p->ncomp;  // launched per component
     d.long_rt = 0;
     d.persist = 1;
     d.lds_tabs = 1;
@@ -1246,7 +1350,7 @@ int build_plan(fm_plan_s* p) {
       rc2 = choose_tile(&d, p->elem, fused_curl ? 3 : 1, (i == 2) && d.gather == fm::G_R2R, d.nb);
     }
     if (rc2) return rc2;
-    d.tiles = ((d.nb + d.B - 1) / d.B) * d.nc * (fused_curl ? 1 : p->ncomp);
+    d.tiles = ((d.nb + d.B - 1) / d.B) * d.nc * (fused_curl ? 1 : d.ncomp);
     set_magics(&d);
     if (i == 2 && wave_capable(d, p->elem) && !(fused_curl && p->elem == 8)) {
       // the per-wavefront kernel, with the most wavefronts per workgroup whose LDS stays
@@ -1254,7 +1358,7 @@ int build_plan(fm_plan_s* p) {
       const int E = default_wave_values(d, p->elem);
       for (const int W : {4, 2, 1}) {
         fm::PassDesc w = d;
-        if (set_wave(&w, p->elem, W, fused_curl ? 1 : p->ncomp, E) && w.lds_bytes <= fm::kSoftLds) {
+        if (set_wave(&w, p->elem, W, fused_curl ? 1 : d.ncomp, E) && w.lds_bytes <= fm::kSoftLds) {
           d = w;
           break;
         }
@@ -1303,8 +1407,21 @@ int launch_one(fm_plan_s* p, int i, const void* in, void* out, hipStream_t st) {
   }
   if (d.wave && !(d.wave == 16 ? d.wtw : d.wtw8)) return FM_E_ARG;
   if (d.fused && d.g.curl && !(d.g.dtab_line && d.g.dtab_b && d.g.dtab_c)) return FM_E_ARG;
-  hipError_t e = (p->prec == FM_F64) ? fm::launch_pass<double>(d, p->dpass + i, in, out, st)
-                                     : fm::launch_pass<float>(d, p->dpass + i, in, out, st);
+  auto run = [&](const fm::PassDesc& dq, const fm::PassDesc* dev, const void* iq, void* oq) {
+    return (p->prec == FM_F64) ? fm::launch_pass<double>(dq, dev, iq, oq, st)
+                               : fm::launch_pass<float>(dq, dev, iq, oq, st);
+  };
+  hipError_t e = run(d, p->dpass + i, in, out);
+  if (p->vec && (i == 0 || i == 4)) {
+    // the other two components, each with its own transform along the swap axis
+    const size_t es_in = p->elem * (d.in_cplx ? 2 : 1), es_out = p->elem * (d.out_cplx ? 2 : 1);
+    for (int q = 1; q < 3 && e == hipSuccess; ++q) {
+      const int slot = vec_slot(i, q);
+      e = run(p->vdesc[slot], p->dpass + fm_plan_s::kPasses + slot,
+              static_cast<const char*>(in) + (size_t)q * d.in_s_comp * es_in,
+              static_cast<char*>(out) + (size_t)q * d.out_s_comp * es_out);
+    }
+  }
   if (e == hipSuccess && sync_debug()) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {
     g_last_hip = (int)e;
@@ -1383,6 +1500,7 @@ int build_batch(int count, const fm_plan* plans, const void* const* rhs_dev, voi
   const int prec = plans[0]->prec;
   for (int i = 0; i < count; ++i) {
     if (plans[i]->prec != prec) return FM_E_ARG;
+    if (plans[i]->vec) return FM_E_KIND;  // vector plans solve one by one
     if (!rhs_dev[i] || !out_dev[i]) return FM_E_NULL;
   }
   b->prec = prec;
@@ -1566,6 +1684,63 @@ int create_plan(fm_plan* out, const int n[3], const double h[3], const int bc[3]
   return FM_OK;
 }
 
+// fm_plan_create_vector: the faces of a mirror-symmetric vector field (periodic and
+// unbounded faces shared; on a symmetric face of axis a, the component along a with one
+// symmetry and the two others with the opposite one).
+int check_vector_faces(const int bc[3][3][2]) {
+  for (int a = 0; a < 3; ++a)
+    for (int f = 0; f < 2; ++f) {
+      const int t[3] = {bc[0][a][f], bc[1][a][f], bc[2][a][f]};
+      for (int q = 0; q < 3; ++q)
+        if (t[q] < FM_BC_EVEN || t[q] > FM_BC_UNB) return FM_E_BC;
+      const bool sym = t[0] <= FM_BC_ODD || t[1] <= FM_BC_ODD || t[2] <= FM_BC_ODD;
+      if (!sym) {
+        if (t[0] != t[1] || t[0] != t[2]) return FM_E_BC;
+        continue;
+      }
+      const int b = (a + 1) % 3, c = (a + 2) % 3;
+      if (t[a] > FM_BC_ODD || t[b] > FM_BC_ODD || t[c] > FM_BC_ODD) return FM_E_BC;
+      if (t[b] != t[c] || t[a] == t[b]) return FM_E_BC;
+    }
+  return FM_OK;
+}
+
+int create_vector_plan(fm_plan* out, const int n[3], const double h[3], const int bc[3][3][2],
+                       int layout, int green, int prec, int kind, hipStream_t st) {
+  if (!out || !n || !h || !bc) return FM_E_NULL;
+  *out = nullptr;
+  int rc = check_enums(layout, green, prec, kind, 3);
+  if (rc) return rc;
+  if (kind == FM_POISSON) return FM_E_KIND;
+  rc = check_vector_faces(bc);
+  if (rc) return rc;
+  fm_plan_s* p = new_plan(n, h, bc[0], layout, green, prec, kind, 3);
+  if (!p) return FM_E_NOMEM;
+  // without a symmetric face the components share their faces: the plain Biot-Savart plan
+  for (int a = 0; a < 3; ++a)
+    for (int f = 0; f < 2; ++f) p->vec = p->vec || bc[0][a][f] <= FM_BC_ODD;
+  for (int q = 0; q < 3; ++q)
+    for (int a = 0; a < 3; ++a)
+      for (int f = 0; f < 2; ++f) p->bcv[q][a][f] = bc[q][a][f];
+  rc = build_plan(p);
+  if (rc == FM_OK) {
+    const hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+      g_last_hip = (int)e;
+      rc = FM_E_HIP;
+    }
+  }
+  if (rc == FM_OK)
+    rc = (prec == FM_F64) ? make_tables_and_green<double>(p, st, false)
+                          : make_tables_and_green<float>(p, st, false);
+  if (rc != FM_OK) {
+    free_plan(p);
+    return rc;
+  }
+  *out = p;
+  return FM_OK;
+}
+
 }  // namespace
 
 namespace fm {
@@ -1609,6 +1784,12 @@ int fm_plan_create(fm_plan* out, const int n[3], const double h[3], const int bc
                    int green, int prec, int kind, int ncomp, void* hip_stream) {
   return create_plan(out, n, h, bc, layout, green, prec, kind, ncomp,
                      reinterpret_cast<hipStream_t>(hip_stream), false);
+}
+
+int fm_plan_create_vector(fm_plan* out, const int n[3], const double h[3], const int bc[3][3][2],
+                          int layout, int green, int prec, int kind, void* hip_stream) {
+  return create_vector_plan(out, n, h, bc, layout, green, prec, kind,
+                            reinterpret_cast<hipStream_t>(hip_stream));
 }
 
 int fm_plan_inspect(const int n[3], const double h[3], const int bc[3][2], int layout, int green,
@@ -1702,6 +1883,7 @@ int fm_plan_spectrum_layout(fm_plan p, int dims[3], int axes[3], int* is_complex
 
 int fm_fft_forward(fm_plan p, const void* in_dev, void* spec_dev, void* workspace_dev, void* hip_stream) {
   if (!p || !in_dev || !spec_dev) return FM_E_NULL;
+  if (p->vec) return FM_E_KIND;  // the spectrum of a vector plan is not exposed
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   char* ws = reinterpret_cast<char*>(workspace_dev);
   if (!ws && !(ws = own_workspace(p))) return FM_E_NOMEM;
@@ -1715,6 +1897,7 @@ int fm_fft_forward(fm_plan p, const void* in_dev, void* spec_dev, void* workspac
 
 int fm_fft_backward(fm_plan p, const void* spec_dev, void* out_dev, void* workspace_dev, void* hip_stream) {
   if (!p || !spec_dev || !out_dev) return FM_E_NULL;
+  if (p->vec) return FM_E_KIND;  // the spectrum of a vector plan is not exposed
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   char* ws = reinterpret_cast<char*>(workspace_dev);
   if (!ws && !(ws = own_workspace(p))) return FM_E_NOMEM;
@@ -1813,7 +1996,7 @@ bool retile(const fm_plan_s* p, int i, int bmax, int mode, fm::PassDesc* out) {
     for (const int W : {4, 2, 1}) {
       fm::PassDesc w = d;
       const int lines = W * fm::wave_lines(d.M, E) * (d.fused ? 1 : wave_plain_pk(d));
-      if (lines > bmax || !set_wave(&w, p->elem, W, fused_curl ? 1 : p->ncomp, E)) continue;
+      if (lines > bmax || !set_wave(&w, p->elem, W, fused_curl ? 1 : d.ncomp, E)) continue;
       if (!pass_in_bounds(w, sizes_in[i], sizes_out[i], p->elem)) return false;
       *out = w;
       return true;
@@ -1824,7 +2007,7 @@ bool retile(const fm_plan_s* p, int i, int bmax, int mode, fm::PassDesc* out) {
   d.lds_tabs = mode != 2;
   if (choose_tile(&d, p->elem, fused_curl ? 3 : 1, (i == 2) && d.gather == fm::G_R2R, d.nb, bmax))
     return false;
-  d.tiles = ((d.nb + d.B - 1) / d.B) * d.nc * (fused_curl ? 1 : p->ncomp);
+  d.tiles = ((d.nb + d.B - 1) / d.B) * d.nc * (fused_curl ? 1 : d.ncomp);
   set_magics(&d);
   if (d.stw && tile_in_span_bytes(d, p->elem) >= (int64_t(1) << 32)) return false;
   if (!pass_in_bounds(d, sizes_in[i], sizes_out[i], p->elem)) return false;
@@ -1848,6 +2031,7 @@ int apply_tiling(fm_plan p, const int lines_per_tile[5], const int persist[5], h
   for (int i = 0; i < 5; ++i) p->pass[i] = next[i];
   FM_HIP(hipMemcpyAsync(p->dpass, p->pass, sizeof(fm::PassDesc) * 5, hipMemcpyHostToDevice, st));
   FM_HIP(hipStreamSynchronize(st));
+  if (p->vec) FM_HIP(upload_vec_descs(p, st));
   return FM_OK;
 }
 
@@ -1871,7 +2055,13 @@ std::string tune_key(const fm_plan_s* p) {
   std::snprintf(buf, sizeof(buf), "%s/%d p%d k%d c%d l%d g%d n%d,%d,%d b%d,%d,%d,%d,%d,%d", arch.c_str(), cus,
                 p->prec, p->kind, p->ncomp, p->layout, p->green, p->n[0], p->n[1], p->n[2], p->bc[0][0],
                 p->bc[0][1], p->bc[1][0], p->bc[1][1], p->bc[2][0], p->bc[2][1]);
-  return buf;
+  std::string key = buf;
+  if (p->vec) {  // the faces of components 1 and 2
+    key += " v";
+    for (int q = 1; q < 3; ++q)
+      for (int a = 0; a < 3; ++a) key += std::to_string(p->bcv[q][a][0]) + std::to_string(p->bcv[q][a][1]);
+  }
+  return key;
 }
 
 bool tune_cache_lookup(const char* path, const std::string& key, int lines[5], int modes[5]) {
@@ -1988,6 +2178,7 @@ int fm_plan_tune(fm_plan p, void* workspace_dev, void* hip_stream) {
       he = hipMemcpyAsync(p->dpass + i, &p->pass[i], sizeof(fm::PassDesc), hipMemcpyHostToDevice, st);
   }
   if (he == hipSuccess) he = hipStreamSynchronize(st);
+  if (he == hipSuccess && p->vec) he = upload_vec_descs(p, st);
   if (he != hipSuccess) {
     g_last_hip = (int)he;
     rc = FM_E_HIP;

@@ -148,7 +148,8 @@ __device__ __forceinline__ void wave_tile(const PassDesc& d, const void* in, voi
   if constexpr (KIND == K_F_CURL) {
 #pragma unroll
     for (int m = 0; m < E; ++m) g[m] = G[grow + fold_index(j + P * m, d.g.fold_line)];
-    const T wc = curl_wave<T>(ti.c, d.g.dtab_c);
+    T wc, mc;
+    curl_c_factor<T>(d.g, curl_wave<T>(ti.c, d.g.dtab_c), wc, mc);
     const T wb = curl_wave<T>(b, d.g.dtab_b);
 #pragma unroll
     for (int m = 0; m < E; ++m) {
@@ -156,14 +157,7 @@ __device__ __forceinline__ void wave_tile(const PassDesc& d, const void* in, voi
       const T wx = d.g.axis_line == 0 ? wl : (d.g.axis_b == 0 ? wb : wc);
       const T wy = d.g.axis_line == 1 ? wl : (d.g.axis_b == 1 ? wb : wc);
       const T wz = d.g.axis_line == 2 ? wl : (d.g.axis_b == 2 ? wb : wc);
-      const cpx<T> fx = v[0][m], fy = v[1][m], fz = v[2][m];
-      // u_hat = G i (w x f_hat)
-      const cpx<T> cx = {wy * fz.x - wz * fy.x, wy * fz.y - wz * fy.y};
-      const cpx<T> cy = {wz * fx.x - wx * fz.x, wz * fx.y - wx * fz.y};
-      const cpx<T> cz = {wx * fy.x - wy * fx.x, wx * fy.y - wy * fx.y};
-      v[0][m] = {-g[m] * cx.y, g[m] * cx.x};
-      v[1][m] = {-g[m] * cy.y, g[m] * cy.x};
-      v[2][m] = {-g[m] * cz.y, g[m] * cz.x};
+      curl_point<T>(g[m], wx, wy, wz, d.g.axis_c, mc, v[0][m], v[1][m], v[2][m]);
     }
   } else {
 #pragma unroll

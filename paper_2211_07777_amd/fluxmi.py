@@ -30,6 +30,7 @@ EXPORTED = [
     "fm_server_create", "fm_server_submit", "fm_server_progress", "fm_server_wait_all",
     "fm_server_get_stats", "fm_server_destroy", "fm_solve_static", "fm_plan_set_tiling",
     "fm_plan_spectrum_layout", "fm_fft_forward", "fm_fft_backward", "fm_plan_tuned_from_cache",
+    "fm_plan_create_vector",
 ]
 STATIC_WORKSPACE_BYTES = 128 << 20  # FM_STATIC_WORKSPACE_BYTES
 
@@ -80,6 +81,8 @@ def library():
     vp, ip, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
     L.fm_plan_create.argtypes = [ctypes.POINTER(vp), ip, dp, ip, ctypes.c_int, ctypes.c_int,
                                  ctypes.c_int, ctypes.c_int, ctypes.c_int, vp]
+    L.fm_plan_create_vector.argtypes = [ctypes.POINTER(vp), ip, dp, ip, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_int, ctypes.c_int, vp]
     L.fm_plan_destroy.argtypes = [vp]
     L.fm_plan_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
     L.fm_plan_shape.argtypes = [vp, ip]
@@ -166,14 +169,26 @@ class Plan:
     """A solver plan (owns the cached Green's spectrum and twiddles on the device)."""
 
     def __init__(self, n, h, bc, layout, green=CHAT2, prec=F64, kind=POISSON, ncomp=None, stream=None):
+        """bc: [[xl, xr], [yl, yr], [zl, zr]], or for Biot-Savart with conditions per component
+        (fm_plan_create_vector) [3][3][2]: per component (x, y, z) such a list."""
         if ncomp is None:
             ncomp = 3 if kind != POISSON else 1
-        self.n, self.h, self.bc = tuple(int(v) for v in n), tuple(float(v) for v in h), [list(p) for p in bc]
+        vector = len(bc) == 3 and all(len(c) == 3 for c in bc)
+        self.n, self.h = tuple(int(v) for v in n), tuple(float(v) for v in h)
+        self.bc = [[list(f) for f in c] for c in bc] if vector else [list(p) for p in bc]
         self.layout, self.green, self.prec, self.kind, self.ncomp = layout, green, prec, kind, ncomp
-        n3, h3, b6 = _args(n, h, bc)
         handle = ctypes.c_void_p()
-        _check(library().fm_plan_create(ctypes.byref(handle), n3, h3, b6, layout, green, prec, kind, ncomp,
-                                        _stream_ptr(stream)), "fm_plan_create")
+        if vector:
+            if ncomp != 3:
+                raise ValueError("conditions per component need ncomp = 3")
+            n3, h3, _ = _args(n, h, bc[0])
+            b18 = (ctypes.c_int * 18)(*[int(v) for c in bc for f in c for v in f])
+            _check(library().fm_plan_create_vector(ctypes.byref(handle), n3, h3, b18, layout, green, prec,
+                                                   kind, _stream_ptr(stream)), "fm_plan_create_vector")
+        else:
+            n3, h3, b6 = _args(n, h, bc)
+            _check(library().fm_plan_create(ctypes.byref(handle), n3, h3, b6, layout, green, prec, kind, ncomp,
+                                            _stream_ptr(stream)), "fm_plan_create")
         self._h = handle
         dims = (ctypes.c_int * 3)()
         _check(library().fm_plan_shape(self._h, dims), "fm_plan_shape")

@@ -50,6 +50,35 @@ int main() {
       else bad += expect(p == nullptr, "plan left on failure", i);
     }
   }
+  // fm_plan_create_vector over faces per component: mirror-symmetric sets (one axis
+  // symmetric or semi-unbounded, or more, which the planner refuses) and broken ones;
+  // without a device a plan that passes planning fails afterwards and is released
+  int vec_planned = 0;
+  for (int i = 0; i < 600; ++i) {
+    int n[3], bcv[3][3][2];
+    double h[3];
+    for (int a = 0; a < 3; ++a) {
+      n[a] = sizes[rng() % (sizeof(sizes) / sizeof(int))] % 200 + 2;
+      h[a] = 0.01 + 0.1 * (rng() % 1000) / 1000.0;
+      const int* pr = pairs[rng() % 10];
+      for (int f = 0; f < 2; ++f)
+        for (int q = 0; q < 3; ++q) {
+          const int t = pr[f];
+          // symmetric faces: the component along a swapped against the two others
+          bcv[q][a][f] = (t <= 1 && q == a) ? 1 - t : t;
+        }
+    }
+    if (rng() % 8 == 0) bcv[rng() % 3][rng() % 3][rng() % 2] = rng() % 4;  // may break the symmetry
+    if (rng() % 40 == 0) bcv[rng() % 3][rng() % 3][rng() % 2] = 9;
+    const int layout = rng() % 2, prec = rng() % 2, kind = 1 + rng() % 4;
+    fm_plan p = nullptr;
+    const int rc = fm_plan_create_vector(&p, n, h, bcv, layout, 0, prec, kind, nullptr);
+    if (rc == FM_OK) fm_plan_destroy(p);
+    else bad += expect(p == nullptr, "vector plan left on failure", i);
+    bad += expect(rc == FM_OK || rc == FM_E_HIP || (rc <= -2 && rc >= -4), fm_error_string(rc), i);
+    if (rc == FM_E_HIP) ++vec_planned;  // planning passed; the stubbed device refused
+  }
+  std::printf("vector plans through planning: %d of 600\n", vec_planned);
   // NULL and invalid arguments of the host-only entry points
   int n[3] = {8, 8, 8}, bc[3][2] = {{3, 3}, {3, 3}, {3, 3}};
   double h[3] = {0.1, 0.1, 0.1};
@@ -59,6 +88,10 @@ int main() {
   bad += expect(fm_plan_inspect(n, h, bc, 5, 0, 0, 0, 1, &info) == FM_E_KIND, "inspect layout", 0);
   bad += expect(fm_plan_inspect(n, h, bc, 0, 0, 0, 0, 0, &info) == FM_E_KIND, "inspect ncomp", 0);
   bad += expect(fm_plan_create(nullptr, n, h, bc, 0, 0, 0, 0, 1, nullptr) == FM_E_NULL, "create NULL", 0);
+  const int bv[3][3][2] = {{{3, 3}, {3, 3}, {1, 1}}, {{3, 3}, {3, 3}, {0, 0}}, {{3, 3}, {3, 3}, {0, 0}}};
+  bad += expect(fm_plan_create_vector(nullptr, n, h, bv, 0, 0, 0, 1, nullptr) == FM_E_NULL, "vector NULL", 0);
+  fm_plan pv = nullptr;
+  bad += expect(fm_plan_create_vector(&pv, n, h, bv, 0, 0, 0, 0, nullptr) == FM_E_KIND, "vector Poisson", 0);
   bad += expect(fm_plan_destroy(nullptr) == FM_OK, "destroy NULL", 0);
   size_t bytes = 0;
   bad += expect(fm_plan_workspace_bytes(nullptr, &bytes) == FM_E_NULL, "workspace NULL", 0);
