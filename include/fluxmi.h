@@ -258,9 +258,11 @@ int fm_plan_device_bytes(fm_plan p, size_t* bytes);
 /* The plan's current tiling per pass: lines per tile, tiles, and the launch mode
  * persist[i]: 1 persistent grid (twiddle tables in LDS), 0 one tile per workgroup with
  * the tables in LDS, 2 one tile per workgroup with the tables read from global memory,
- * 3 the per-wavefront fused kernel (complex lines of a power-of-two length from 32 to
- * 1024 along the last axis: each 64-lane wavefront transforms, multiplies and inverts
- * whole lines in registers; lines_per_tile is then the lines of one workgroup). */
+ * 3, 4 and 5 the per-wavefront kernels with 16, 8 and 32 values per lane (lines of a
+ * power-of-two length: each 64-lane wavefront transforms whole lines in registers,
+ * exchanging values through its own LDS; for the fused pass it also multiplies and
+ * inverts them; lines_per_tile is then the lines of one workgroup).  Mode 5 serves the
+ * fused pass of FP32 Poisson plans only. */
 int fm_plan_tiling(fm_plan p, int lines_per_tile[5], int tiles[5], int persist[5]);
 
 /* Set the tiling of every pass, as fm_plan_tiling reports it (for example a tiling that

@@ -196,6 +196,45 @@ struct SmallDft<16, S, T> {
   }
 };
 
+// radix 32 = 2 x 16: the DFTs of the even and the odd samples, joined with W32^k
+template <int S, typename T>
+struct SmallDft<32, S, T> {
+  __device__ __forceinline__ static void run(cpx<T>* v) {
+    // cos / sin of 2 pi k / 32, k = 0..15
+    constexpr double C[16] = {1.0, 0.98078528040323044913, 0.92387953251128675613,
+                              0.83146961230254523708, 0.70710678118654752440,
+                              0.55557023301960222474, 0.38268343236508977173,
+                              0.19509032201612826785, 0.0, -0.19509032201612826785,
+                              -0.38268343236508977173, -0.55557023301960222474,
+                              -0.70710678118654752440, -0.83146961230254523708,
+                              -0.92387953251128675613, -0.98078528040323044913};
+    constexpr double Sn[16] = {0.0, 0.19509032201612826785, 0.38268343236508977173,
+                               0.55557023301960222474, 0.70710678118654752440,
+                               0.83146961230254523708, 0.92387953251128675613,
+                               0.98078528040323044913, 1.0, 0.98078528040323044913,
+                               0.92387953251128675613, 0.83146961230254523708,
+                               0.70710678118654752440, 0.55557023301960222474,
+                               0.38268343236508977173, 0.19509032201612826785};
+    cpx<T> e[16], o[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      e[m] = v[2 * m];
+      o[m] = v[2 * m + 1];
+    }
+    SmallDft<16, S, T>::run(e);
+    SmallDft<16, S, T>::run(o);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      cpx<T> t;
+      if (k == 0) t = o[0];
+      else if (k == 8) t = mul_si<S>(o[8]);
+      else t = cmul(o[k], cpx<T>{T(C[k]), T(S * Sn[k])});
+      v[k] = cadd(e[k], t);
+      v[k + 16] = csub(e[k], t);
+    }
+  }
+};
+
 constexpr int gather_of(int k) {
   return (k == K_C2C_F || k == K_C2C_I || k == K_F_C2C || k == K_F_CURL) ? G_CPLX
          : (k == K_R2C || k == K_F_R2C)                                   ? G_REAL2

@@ -26,13 +26,15 @@ static hipError_t allow_full_lds() {
 
 // Fused complex passes in the per-wavefront kernel with E values per lane: d.B /
 // wave_lines(M, E) wavefronts per workgroup, one workgroup per tile.  Three-component
-// (curl) lines of 16 values per lane are built in FP32 only (in FP64 they would hold 48
-// complex doubles per lane).
+// (curl) lines of 16 values per lane are built in FP32, and in FP64 for 1024-point lines
+// only; 32 values per lane (one LDS exchange per transform up to 1024 points) for FP32
+// Poisson lines only (three components, or FP64, would not fit the registers).
 template <int KIND, int E>
 static hipError_t launch_wave_e(const PassDesc& d, const PassDesc* dev, const void* in, void* out,
                                 hipStream_t st) {
   if constexpr (wave_length(FM_MC, E) &&
-                (KIND == K_F_C2C || (KIND == K_F_CURL && (sizeof(FM_T) == 4 || E == 8 || FM_MC == 1024)))) {
+                ((KIND == K_F_C2C && (E != 32 || sizeof(FM_T) == 4)) ||
+                 (KIND == K_F_CURL && E != 32 && (sizeof(FM_T) == 4 || E == 8 || FM_MC == 1024)))) {
     const int threads = 64 * (d.B / wave_lines(FM_MC, E));
     if (threads < 64 || threads > kThreads) return hipErrorInvalidValue;
     if (d.lds_bytes > kSoftLds) {
@@ -86,6 +88,7 @@ static hipError_t launch_wave(const PassDesc& d, const PassDesc* dev, const void
   if constexpr (fused_of(KIND)) {
     if (d.wave == 16) return launch_wave_e<KIND, 16>(d, dev, in, out, st);
     if (d.wave == 8) return launch_wave_e<KIND, 8>(d, dev, in, out, st);
+    if (d.wave == 32) return launch_wave_e<KIND, 32>(d, dev, in, out, st);
   } else {
     if (d.wave == 16) return launch_wave_plain_e<KIND, 16>(d, dev, in, out, st);
     if (d.wave == 8) return launch_wave_plain_e<KIND, 8>(d, dev, in, out, st);

@@ -158,7 +158,7 @@ constexpr int fft_line_stride(int M) { return M + (M >> 4) + 1; }
 // 1 <= r < R, k < Ns) from a table at wave_tw_offset(M, s, E) + (r-1) Ns + k.
 constexpr int kWaveValues = 16;
 constexpr bool wave_length(int M, int E = kWaveValues) {
-  return (E == 8 || E == 16) && M >= 2 * E && M <= 64 * E && (M & (M - 1)) == 0;
+  return (E == 8 || E == 16 || E == 32) && M >= 2 * E && M <= 64 * E && (M & (M - 1)) == 0;
 }
 constexpr int wave_radix(int M, int s, int E = kWaveValues) {
   int rest = M / E;
@@ -267,6 +267,7 @@ struct PassDesc {
   int32_t wave_rs;          // plain passes: raw tile line stride, in input elements
   const void* wtw;          // its stage twiddle tables: E = 16 (wave_tw_size(M, 16) entries)
   const void* wtw8;         // and E = 8
+  const void* wtw32;        // and E = 32 (FP32 Poisson fused passes)
 };
 
 // Sampling description of the Green's function for the spectrum generation (FP64).

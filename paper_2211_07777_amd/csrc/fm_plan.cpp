@@ -265,7 +265,7 @@ struct fm_plan_s {
   std::map<int, void*> stw;
   std::map<int, void*> tw64;
   int tuned_from_cache = 0;  // the last fm_plan_tune applied a FLUXMI_TUNE_CACHE entry
-  std::map<int, void*> wtw;  // stage twiddles of the per-wavefront kernels, by (M << 5) | E
+  std::map<int, void*> wtw;  // stage twiddles of the per-wavefront kernels, by (M << 6) | E
   void* dtab = nullptr;      // central-difference symbols of the curl (line, b, c tables)
   void* ws_internal = nullptr;
   std::mutex ws_mu;  // guards the lazy allocation of ws_internal
@@ -442,6 +442,7 @@ int wave_plain_rs(const fm::PassDesc& d, int E);
 bool wave_capable(const fm::PassDesc& d, size_t elem, int E) {
   // the kernels are compiled with the compile-time-length classes (fm_inst.hip)
   if (d.long_rt || !fm::wave_length(d.M, E) || !fm::is_fast_len(d.M)) return false;
+  if (E == 32 && (!d.fused || d.g.curl || elem != 4)) return false;  // FP32 Poisson lines only
   if (!d.fused) return wave_plain_rs(d, E) > 0;
   if (d.gather != fm::G_CPLX) return false;
   if (d.g.curl && elem != 4 && E == 16 && d.M != 1024) return false;
@@ -649,10 +650,10 @@ int make_tables_and_green(fm_plan_s* p, hipStream_t st, bool deferred) {
   for (int i = 0; i < 5; ++i) {
     fm::PassDesc w = p->pass[i];
     w.long_rt = 0;  // the per-wavefront kernels take the compile-time length class
-    for (const int E : {16, 8}) {
+    for (const int E : {16, 8, 32}) {
       if (!wave_capable(w, p->elem, E)) continue;
       const int M = p->pass[i].M;
-      const int key = (M << 5) | E;
+      const int key = (M << 6) | E;
       if (!p->wtw.count(key)) {
         void* ptr = nullptr;
         const size_t n = (size_t)std::max(1, fm::wave_tw_size(M, E));
@@ -661,7 +662,7 @@ int make_tables_and_green(fm_plan_s* p, hipStream_t st, bool deferred) {
         p->table_bytes += sizeof(T) * 2 * n;
         FM_HIP(fm::launch_wave_twiddles<T>(ptr, M, E, st));
       }
-      (E == 16 ? p->pass[i].wtw : p->pass[i].wtw8) = p->wtw[key];
+      (E == 16 ? p->pass[i].wtw : (E == 8 ? p->pass[i].wtw8 : p->pass[i].wtw32)) = p->wtw[key];
     }
   }
 
@@ -1405,7 +1406,7 @@ int launch_one(fm_plan_s* p, int i, const void* in, void* out, hipStream_t st) {
                  d.M, p->prec == FM_F64 ? "f64" : "f32", d.tiles, d.B, d.lds_bytes);
     std::fflush(stderr);
   }
-  if (d.wave && !(d.wave == 16 ? d.wtw : d.wtw8)) return FM_E_ARG;
+  if (d.wave && !(d.wave == 16 ? d.wtw : (d.wave == 8 ? d.wtw8 : d.wtw32))) return FM_E_ARG;
   if (d.fused && d.g.curl && !(d.g.dtab_line && d.g.dtab_b && d.g.dtab_c)) return FM_E_ARG;
   auto run = [&](const fm::PassDesc& dq, const fm::PassDesc* dev, const void* iq, void* oq) {
     return (p->prec == FM_F64) ? fm::launch_pass<double>(dq, dev, iq, oq, st)
@@ -1961,7 +1962,7 @@ int fm_solve_batched(int count, const fm_plan* plans, const void* const* rhs_dev
 // tables, 0 one tile per workgroup with LDS tables, 2 one tile per workgroup with global
 // tables (the only mode of the runtime-length and long FP64 kernels).
 int launch_mode(const fm::PassDesc& d, size_t elem) {
-  if (d.wave) return d.wave == 16 ? 3 : 4;
+  if (d.wave) return d.wave == 16 ? 3 : (d.wave == 8 ? 4 : 5);
   const bool pipelined = compile_time_kernel(d, elem) && fm::pipelined_kernel((int)elem, d.M);
   if (!pipelined || !d.lds_tabs) return 2;
   return d.persist ? 1 : 0;
@@ -1969,7 +1970,8 @@ int launch_mode(const fm::PassDesc& d, size_t elem) {
 
 // A pass re-tiled with at most bmax lines per tile, in launch mode `mode` (1 persistent
 // with LDS tables, 0 one tile per workgroup with LDS tables, 2 one tile per workgroup
-// with global tables, 3 / 4 the per-wavefront kernels with 16 / 8 values per lane);
+// with global tables, 3 / 4 / 5 the per-wavefront kernels with 16 / 8 / 32 values per
+// lane);
 // false if no such tiling is valid for this plan (the compile-time-length kernels
 // address a tile with 32-bit offsets).
 bool retile(const fm_plan_s* p, int i, int bmax, int mode, fm::PassDesc* out) {
@@ -1980,13 +1982,14 @@ bool retile(const fm_plan_s* p, int i, int bmax, int mode, fm::PassDesc* out) {
   d.wave = 0;
   // the per-wavefront kernel has the compile-time length; the LDS-tile kernel takes the
   // class the plan chose
-  d.long_rt = (mode == 3 || mode == 4) ? 0 : p->long_rt[i];
+  const bool wave_mode = mode >= 3;
+  d.long_rt = wave_mode ? 0 : p->long_rt[i];
   d.stw = p->stw_plan[i];
-  if (mode == 3 || mode == 4) {
+  if (wave_mode) {
     // the per-wavefront kernel (16 or 8 values per lane): the most wavefronts per
     // workgroup within bmax lines; launched in the compile-time class, which the stage
     // table selects
-    const int E = mode == 3 ? 16 : 8;
+    const int E = mode == 3 ? 16 : (mode == 4 ? 8 : 32);
     if (!wave_capable(d, p->elem, E)) return false;
     if (!d.stw) {
       const auto t = p->stw.find(d.M);
@@ -2023,7 +2026,7 @@ int apply_tiling(fm_plan p, const int lines_per_tile[5], const int persist[5], h
   fm::PassDesc next[5];
   for (int i = 0; i < 5; ++i) {
     const int mode = persist[i];
-    if (lines_per_tile[i] < 1 || mode < 0 || mode > 4) return FM_E_ARG;
+    if (lines_per_tile[i] < 1 || mode < 0 || mode > 5) return FM_E_ARG;
     if (!retile(p, i, lines_per_tile[i], mode, &next[i])) return FM_E_ARG;
     // exactly the requested tiling (retile takes the largest tile up to the bound)
     if (next[i].B != lines_per_tile[i] || launch_mode(next[i], p->elem) != mode) return FM_E_ARG;
@@ -2159,7 +2162,7 @@ int fm_plan_tune(fm_plan p, void* workspace_dev, void* hip_stream) {
     he = time_pass(i, best, &best_ms);
     std::vector<std::pair<int, int>> seen{{best.B, launch_mode(best, p->elem)}};
     for (const int bmax : {64, 32, 16, 8, 4, 2, 1}) {
-      for (const int mode : {1, 0, 2, 3, 4}) {
+      for (const int mode : {1, 0, 2, 3, 4, 5}) {
         fm::PassDesc d;
         if (he != hipSuccess || !retile(p, i, bmax, mode, &d)) continue;
         const std::pair<int, int> key{d.B, launch_mode(d, p->elem)};

@@ -112,7 +112,7 @@ __device__ __forceinline__ void wave_tile(const PassDesc& d, const void* in, voi
   const TileIdx ti = tile_index(d, tile);
   if (l >= ti.nl) return;  // no workgroup barrier follows
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem) + (size_t)(wave * L + lane / P) * fft_line_stride(M);
-  const GTab<T> tw = gptr<cpx<T>>(E == 16 ? d.wtw : d.wtw8);
+  const GTab<T> tw = gptr<cpx<T>>(E == 16 ? d.wtw : (E == 8 ? d.wtw8 : d.wtw32));
   const int b = ti.b0 + l;
   const int comp0 = NCL == 3 ? 0 : ti.comp;
   const int64_t line_off = (int64_t)ti.c * d.in_s_c + (int64_t)b * d.in_s_b;

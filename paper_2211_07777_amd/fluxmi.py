@@ -310,8 +310,9 @@ class Plan:
 
     def tiling(self):
         """(lines per tile, tiles, launch mode) of the five passes; mode 1 = persistent
-        grid, 0 = one tile per workgroup with LDS tables, 2 = with global tables, 3 / 4 =
-        the per-wavefront kernels with 16 / 8 values per lane."""
+        grid, 0 = one tile per workgroup with LDS tables, 2 = with global tables, 3 / 4 / 5 =
+        the per-wavefront kernels with 16 / 8 / 32 values per lane (5: FP32 Poisson fused
+        pass only)."""
         b, t, q = (ctypes.c_int * 5)(), (ctypes.c_int * 5)(), (ctypes.c_int * 5)()
         _check(library().fm_plan_tiling(self._h, b, t, q), "fm_plan_tiling")
         return {"lines_per_tile": list(b), "tiles": list(t), "persistent": list(q)}

@@ -190,7 +190,8 @@ def test_batched_bitwise_equals_single(prec):
 @pytest.mark.parametrize("M", [32, 64, 128, 256, 512, 1024])
 def test_per_wavefront_fused_kernel(M, prec, tol):
     """The per-wavefront fused kernel at every power-of-two line length it serves, with 16
-    values per lane (launch mode 3) and 8 (mode 4, lines of at most 512), 1, 2 and 4
+    values per lane (launch mode 3), 8 (mode 4, lines of at most 512) and 32 (mode 5, FP32
+    Poisson lines of at least 64 points), 1, 2 and 4
     wavefronts per workgroup (ragged last tiles): unbounded and periodic last axes, both
     layouts, two right-hand sides per solve, and the spectral curl."""
     rng = np.random.default_rng(M + 7 * prec)
@@ -212,9 +213,11 @@ def test_per_wavefront_fused_kernel(M, prec, tol):
             ref = np.stack([oracle_solve(f[c] if ncomp > 1 else f, n, h, bc, layout) for c in range(ncomp)])
             ref = ref if ncomp > 1 else ref[0]
         ran = 0
-        for values, mode in ((16, 3), (8, 4)):
+        for values, mode in ((16, 3), (8, 4), (32, 5)):
             if M // values > 64 or M < 2 * values:
                 continue
+            if values == 32 and (prec != F.F32 or kind != F.POISSON):
+                continue  # 32 values per lane: FP32 Poisson lines only
             if kind == F.BIOT_SAVART and prec == F.F64 and values == 16 and M != 1024:
                 continue  # built for 1024-point lines only (one line per wavefront)
             lines = 64 // (M // values)
