@@ -2136,22 +2136,33 @@ int fm_plan_tune(fm_plan p, void* workspace_dev, void* hip_stream) {
   const void* ins[5];
   void* outs[5];
   bind_buffers(p, rhs, out, ws, ins, outs);
-  // time one pass with descriptor d (uploaded to the plan's device slot): best of reps
+  // time one pass with descriptor d (uploaded to the plan's device slot): a sample is n
+  // launches back to back between two events, n chosen so that a sample lasts about 0.2
+  // ms (launch jitter of passes of ten microseconds would otherwise decide); best of 3
   auto time_pass = [&](int i, const fm::PassDesc& d, float* ms) -> hipError_t {
     hipError_t e = hipMemcpyAsync(p->dpass + i, &d, sizeof(fm::PassDesc), hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return e;
     e = hipStreamSynchronize(st);
-    float best = 1e30f;
-    for (int r = 0; r < 8 && e == hipSuccess; ++r) {
-      e = hipEventRecord(e0, st);
-      if (e == hipSuccess)
-        e = (p->prec == FM_F64) ? fm::launch_pass<double>(d, p->dpass + i, ins[i], outs[i], st)
+    auto sample = [&](int n, float* t) {
+      hipError_t r = hipEventRecord(e0, st);
+      for (int k = 0; k < n && r == hipSuccess; ++k)
+        r = (p->prec == FM_F64) ? fm::launch_pass<double>(d, p->dpass + i, ins[i], outs[i], st)
                                 : fm::launch_pass<float>(d, p->dpass + i, ins[i], outs[i], st);
-      if (e == hipSuccess) e = hipEventRecord(e1, st);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      if (r == hipSuccess) r = hipEventRecord(e1, st);
+      if (r == hipSuccess) r = hipEventSynchronize(e1);
+      if (r == hipSuccess) r = hipEventElapsedTime(t, e0, e1);
+      *t /= (float)n;
+      return r;
+    };
+    float t1 = 0.f;
+    if (e == hipSuccess) e = sample(1, &t1);  // warms up
+    if (e == hipSuccess) e = sample(1, &t1);
+    const int n = std::max(1, std::min(64, (int)std::ceil(0.2f / std::max(t1, 1e-4f))));
+    float best = 1e30f;
+    for (int r = 0; r < 3 && e == hipSuccess; ++r) {
       float t = 0.f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
-      if (r > 0) best = std::min(best, t);  // the first run warms up
+      e = sample(n, &t);
+      best = std::min(best, t);
     }
     *ms = best;
     return e;
