@@ -218,3 +218,20 @@ def test_vector_refusals():
     ref = O.solve(f, [8, 6, 8], h, shared[0], F.CELL, 0, 1)
     assert rel_linf(gpu_solve(plan, f), ref) < TOL64
     plan.close()
+
+
+@pytest.mark.parametrize("green", [F.HEJ4, F.LGF2])
+@pytest.mark.parametrize("layout", [F.CELL, F.NODE])
+def test_vector_regularised_kernels(green, layout):
+    """A semi-unbounded swap axis and two unbounded ones are three convolution directions,
+    so the regularised kernels (HEJ) and the lattice Green's function apply: FP64 parity
+    against the oracle with the same kernel, on both sides of the swap axis."""
+    for axis, tang in ((0, (E, U)), (2, (U, OD))):
+        other = {a: (U, U) for a in range(3) if a != axis}
+        n, h = [16, 14, 12], [0.07, 0.08, 0.09]
+        bcv = faces(axis, tang, other)
+        f = np.random.default_rng(31 + axis + 2 * layout).standard_normal((3,) + O.user_shape(n, layout))
+        ref = O.solve_vector(f, n, h, bcv, layout, green, F.BIOT_SAVART)
+        plan = F.Plan(n, h, bcv, layout, green, F.F64, F.BIOT_SAVART)
+        _run(plan, f, ref, TOL64, O.swap_faces(bcv), layout, (green, axis))
+        plan.close()
