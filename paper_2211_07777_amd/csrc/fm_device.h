@@ -722,44 +722,49 @@ __device__ __forceinline__ T signed_wave(int k, int M, T dw) {
   return dw * T(ks);
 }
 
-// u_hat = G i (w x f_hat) at one spectral point (Sec. V), in place.  The wavenumber of
-// the c direction (physical axis ac) may be imaginary, i m (a symmetric c direction,
-// GreenRef::csym; its real part wx / wy / wz is then 0): its terms i m (e_c x f) are
-// added under a branch that is uniform across the wavefront.
+// u_hat = G i (w x f_hat) at one spectral point (Sec. V), in place.  The wavenumbers of
+// the b and c directions (physical axes ab, ac) may be imaginary, i mb / i mc (symmetric
+// directions, GreenRef::csym_b / csym; their real parts are then 0): their terms
+// i m (e x f) are added under branches that are uniform across the wavefront.
 template <typename T>
-__device__ __forceinline__ void curl_point(T g, T wx, T wy, T wz, int ac, T m, cpx<T>& fx, cpx<T>& fy,
-                                           cpx<T>& fz) {
+__device__ __forceinline__ void curl_imag(int a, T m, const cpx<T>& fx, const cpx<T>& fy,
+                                          const cpx<T>& fz, cpx<T>& cx, cpx<T>& cy, cpx<T>& cz) {
+  // i m (e_a x f): e_x x f = (0, -f_z, f_y), e_y x f = (f_z, 0, -f_x), e_z x f = (-f_y, f_x, 0)
+  auto add = [m](cpx<T>& c, const cpx<T>& f, T sg) {  // c += sg i m f
+    c.x -= sg * m * f.y;
+    c.y += sg * m * f.x;
+  };
+  if (a == 0) {
+    add(cy, fz, T(-1));
+    add(cz, fy, T(1));
+  } else if (a == 1) {
+    add(cx, fz, T(1));
+    add(cz, fx, T(-1));
+  } else {
+    add(cx, fy, T(-1));
+    add(cy, fx, T(1));
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void curl_point(T g, T wx, T wy, T wz, int ac, T m, int ab, T mb,
+                                           cpx<T>& fx, cpx<T>& fy, cpx<T>& fz) {
   cpx<T> cx = {wy * fz.x - wz * fy.x, wy * fz.y - wz * fy.y};
   cpx<T> cy = {wz * fx.x - wx * fz.x, wz * fx.y - wx * fz.y};
   cpx<T> cz = {wx * fy.x - wy * fx.x, wx * fy.y - wy * fx.y};
-  if (m != T(0)) {
-    // i m (e_c x f): e_x x f = (0, -f_z, f_y), e_y x f = (f_z, 0, -f_x), e_z x f = (-f_y, f_x, 0)
-    auto add = [m](cpx<T>& c, const cpx<T>& f, T sg) {  // c += sg i m f
-      c.x -= sg * m * f.y;
-      c.y += sg * m * f.x;
-    };
-    if (ac == 0) {
-      add(cy, fz, T(-1));
-      add(cz, fy, T(1));
-    } else if (ac == 1) {
-      add(cx, fz, T(1));
-      add(cz, fx, T(-1));
-    } else {
-      add(cx, fy, T(-1));
-      add(cy, fx, T(1));
-    }
-  }
+  if (m != T(0)) curl_imag<T>(ac, m, fx, fy, fz, cx, cy, cz);
+  if (mb != T(0)) curl_imag<T>(ab, mb, fx, fy, fz, cx, cy, cz);
   fx = {-g * cx.y, g * cx.x};
   fy = {-g * cy.y, g * cy.x};
   fz = {-g * cz.y, g * cz.x};
 }
 
-// The c-direction factor of the curl: (real, imaginary) = (w, 0) on a DFT direction,
-// (0, -s w) on a symmetric or semi-unbounded one (GreenRef::csym = s).
+// A direction's factor in the curl: (real, imaginary) = (w, 0) on a DFT direction,
+// (0, -s w) on a symmetric or semi-unbounded one (s = GreenRef::csym or csym_b).
 template <typename T>
-__device__ __forceinline__ void curl_c_factor(const GreenRef& gr, T w, T& re, T& im) {
-  re = gr.csym ? T(0) : w;
-  im = gr.csym ? T(-gr.csym) * w : T(0);
+__device__ __forceinline__ void curl_factor(int s, T w, T& re, T& im) {
+  re = s ? T(0) : w;
+  im = s ? T(-s) * w : T(0);
 }
 
 // Derivative factor of DFT mode k in the curl, from the direction's table: the spectral
@@ -827,8 +832,17 @@ __device__ __forceinline__ void plain_store(const PassDesc& d, void* out, const 
     else store_real<T, MC, false>(d, out, ti, out_off, val);
   } else {
     auto val = [&](int l, int j) { return scatter_r2r<T>(buf, ls, d.r2r, tw, l, j); };
-    if (d.has_fix) store_real<T, MC, true>(d, out, ti, out_off, val);
-    else store_real<T, MC, false>(d, out, ti, out_off, val);
+    if (d.out_cplx) {
+      // the real-to-real spectrum handed on as complex values with a zero imaginary part
+      // (the next axis is transformed as a full complex DFT)
+      auto cval = [&](int l, int j) { return cpx<T>{val(l, j), T(0)}; };
+      store_tile<false>(reinterpret_cast<cpx<T>*>(out) + out_off, d.out_s_line, d.out_s_b, d.out_s_c,
+                        nl, d.out_n, d.mag_out, d.B, d.mag_B, ti.b0, ti.c, d.fix, cval);
+    } else if (d.has_fix) {
+      store_real<T, MC, true>(d, out, ti, out_off, val);
+    } else {
+      store_real<T, MC, false>(d, out, ti, out_off, val);
+    }
   }
 }
 
@@ -1054,7 +1068,7 @@ __device__ void fused_compute(const PassDesc& d, void* out, const TileIdx& ti, c
     fft_lines<T, MC, +1>(buf, ls, F, d, tb.stw, lds_g, min(d.out_n, M));
   } else {
     T wc, mc;
-    curl_c_factor<T>(d.g, curl_wave<T>(c, d.g.dtab_c), wc, mc);
+    curl_factor<T>(d.g.csym, curl_wave<T>(c, d.g.dtab_c), wc, mc);
     struct Tri {
       cpx<T> x, y, z;
     };
@@ -1064,14 +1078,15 @@ __device__ void fused_compute(const PassDesc& d, void* out, const TileIdx& ti, c
           const int l = e / M, k = e - l * M;
           const T g = gl[l * FL + fold_index(k, d.g.fold_line)];
           const T wl = curl_wave<T>(k, d.g.dtab_line);
-          const T wb = curl_wave<T>(b0 + l, d.g.dtab_b);
+          T wb, mb;
+          curl_factor<T>(d.g.csym_b, curl_wave<T>(b0 + l, d.g.dtab_b), wb, mb);
           const T wx = d.g.axis_line == 0 ? wl : (d.g.axis_b == 0 ? wb : wc);
           const T wy = d.g.axis_line == 1 ? wl : (d.g.axis_b == 1 ? wb : wc);
           const T wz = d.g.axis_line == 2 ? wl : (d.g.axis_b == 2 ? wb : wc);
           cpx<T> fx = buf[(0 * nl + l) * ls + pad16(k)];
           cpx<T> fy = buf[(1 * nl + l) * ls + pad16(k)];
           cpx<T> fz = buf[(2 * nl + l) * ls + pad16(k)];
-          curl_point<T>(g, wx, wy, wz, d.g.axis_c, mc, fx, fy, fz);
+          curl_point<T>(g, wx, wy, wz, d.g.axis_c, mc, d.g.axis_b, mb, fx, fy, fz);
           return Tri{fx, fy, fz};
         },
         [&](int e, const Tri& v) {

@@ -113,8 +113,9 @@ struct GreenRef {
   // after a sine transform and -1 after a cosine one (both flipped on a reversed axis).
   // The kernels form u_hat = G i (w x f_hat); only the two components tangential to c
   // (which share their faces, hence s) enter its c-direction terms, so the c factor
-  // becomes the complex -i s w.  csym = s, or 0 when c is a DFT direction.
-  int32_t csym;
+  // becomes the complex -i s w.  csym = s, or 0 when c is a DFT direction; csym_b the
+  // same for the b direction (a second symmetric axis).
+  int32_t csym, csym_b;
 };
 
 

@@ -277,16 +277,23 @@ struct fm_plan_s {
   std::vector<fm::PassDesc> gen_desc;
   int device = 0;
   size_t table_bytes = 0;  // device memory of the plan's tables (Green, twiddles, descriptors)
-  // fm_plan_create_vector: faces per component (bc above holds component 0's).  The one
+  // fm_plan_create_vector: faces per component (bc above holds component 0's).  The
   // symmetric or semi-unbounded axis is the first transformed (a0); passes 1 and 5 run
   // once per component, each with its own real-to-real transform (the input's kind
   // forward, the swapped kind of the output backward), on a spectrum indexed by
   // frequency shared by the three components.  Device descriptors of components 1 and 2
   // follow the kPasses at dpass[kPasses + vec_slot(pass, comp)].
   bool vec = false;
+  // a second symmetric axis (transformed by passes 2 and 4, also once per component): the
+  // DFT axis is then transformed as a full complex DFT, pass 2 writes complex values with
+  // a zero imaginary part and pass 4 reads their real parts
+  bool vec2 = false;
   int bcv[3][3][2] = {};
-  fm::R2R vr2r[3][2] = {};  // [component][0: pass 1 forward, 1: pass 5 backward]
-  static constexpr int kVecDesc = 4;
+  // [component][0: pass 1 forward, 1: pass 5 backward, 2: pass 2 forward, 3: pass 4 backward]
+  fm::R2R vr2r[3][4] = {};
+  fm::Fixup vfix[3] = {};  // pass 5's output conventions per component (its faces)
+  int vhas_fix[3] = {};
+  static constexpr int kVecDesc = 8;
   fm::PassDesc vdesc[kVecDesc];  // host copies of the device slots (vec_slot)
 };
 
@@ -443,6 +450,7 @@ bool wave_capable(const fm::PassDesc& d, size_t elem, int E) {
   // the kernels are compiled with the compile-time-length classes (fm_inst.hip)
   if (d.long_rt || !fm::wave_length(d.M, E) || !fm::is_fast_len(d.M)) return false;
   if (E == 32 && (!d.fused || d.g.curl || elem != 4)) return false;  // FP32 Poisson lines only
+  if (!d.fused && d.gather == fm::G_R2R && d.out_cplx) return false;  // LDS-tile kernel only
   if (!d.fused) return wave_plain_rs(d, E) > 0;
   if (d.gather != fm::G_CPLX) return false;
   if (d.g.curl && elem != 4 && E == 16 && d.M != 1024) return false;
@@ -587,19 +595,32 @@ void release_generation(fm_plan_s* p) {
   p->tw64.clear();
 }
 
-// Device slot, after the kPasses, of component q (1 or 2) of pass i (0 or 4) of a vector
-// plan.
-int vec_slot(int i, int q) { return (i == 0 ? 0 : 2) + (q - 1); }
+// Whether pass i of a plan runs once per component (vector plans: passes 1 and 5, and 2
+// and 4 with a second symmetric axis).
+bool vec_pass(const fm_plan_s* p, int i) {
+  return p->vec && (i == 0 || i == 4 || (p->vec2 && (i == 1 || i == 3)));
+}
+// Per-component transform of pass i (vr2r's second index).
+int vec_r2r(int i) { return i == 0 ? 0 : (i == 4 ? 1 : (i == 1 ? 2 : 3)); }
+// Device slot, after the kPasses, of component q (1 or 2) of pass i of a vector plan.
+int vec_slot(int i, int q) { return 2 * vec_r2r(i) + (q - 1); }
 
-// The descriptors of components 1 and 2 of passes 1 and 5 of a vector plan, rebuilt from
-// the plan's (component 0) descriptors with their own transforms, and uploaded.
+// The descriptors of components 1 and 2 of the per-component passes of a vector plan,
+// rebuilt from the plan's (component 0) descriptors with their own transforms, and
+// uploaded.
 hipError_t upload_vec_descs(fm_plan_s* p, hipStream_t st) {
-  for (const int i : {0, 4})
+  for (const int i : {0, 1, 3, 4}) {
+    if (!vec_pass(p, i)) continue;
     for (int q = 1; q < 3; ++q) {
       fm::PassDesc& d = p->vdesc[vec_slot(i, q)];
       d = p->pass[i];
-      d.r2r = p->vr2r[q][i == 0 ? 0 : 1];
+      d.r2r = p->vr2r[q][vec_r2r(i)];
+      if (i == 4) {
+        d.fix = p->vfix[q];
+        d.has_fix = p->vhas_fix[q];
+      }
     }
+  }
   const hipError_t e = hipMemcpyAsync(p->dpass + fm_plan_s::kPasses, p->vdesc, sizeof(p->vdesc),
                                       hipMemcpyHostToDevice, st);
   return e == hipSuccess ? hipStreamSynchronize(st) : e;
@@ -1068,7 +1089,7 @@ int build_plan(fm_plan_s* p) {
   // conditions per component (fm_plan_create_vector): the transforms of every component,
   // of the source (vin) and of the velocity (vout, even and odd faces swapped)
   AxisPlan vin[3][3], vout[3][3];
-  int swap_axis = -1;
+  bool swap[3] = {false, false, false};
   if (p->vec) {
     auto sw = [](int b) { return b == FM_BC_EVEN ? FM_BC_ODD : (b == FM_BC_ODD ? FM_BC_EVEN : b); };
     for (int q = 0; q < 3; ++q)
@@ -1078,27 +1099,32 @@ int build_plan(fm_plan_s* p) {
         rc = plan_axis(p->n[a], p->h[a], node, sw(p->bcv[q][a][0]), sw(p->bcv[q][a][1]), &vout[q][a]);
         if (rc) return rc;
       }
-    // one symmetric or semi-unbounded axis; the two others periodic or unbounded
+    // one or two symmetric or semi-unbounded axes; at least one periodic or unbounded
+    int nswap = 0;
     for (int a = 0; a < 3; ++a)
       if (!p->ax[a].dft) {
-        if (swap_axis >= 0) return FM_E_KIND;
-        swap_axis = a;
+        swap[a] = true;
+        ++nswap;
       }
-    if (swap_axis < 0) return FM_E_KIND;
-    // spectral extent along it: every frequency index of the components' kinds
-    int ns = 0;
-    for (int q = 0; q < 3; ++q) {
-      const AxisPlan& ai = vin[q][swap_axis];
-      const AxisPlan& ao = vout[q][swap_axis];
-      ns = std::max(ns, kind_form(ai.fwd).qout + ai.nin);
-      ns = std::max(ns, kind_form(ao.bwd).pin + ao.nin);
+    if (nswap == 0 || nswap == 3) return FM_E_KIND;
+    p->vec2 = nswap == 2;
+    // spectral extent along each: every frequency index of the components' kinds
+    for (int a = 0; a < 3; ++a) {
+      if (!swap[a]) continue;
+      int ns = 0;
+      for (int q = 0; q < 3; ++q) {
+        const AxisPlan& ai = vin[q][a];
+        const AxisPlan& ao = vout[q][a];
+        ns = std::max(ns, kind_form(ai.fwd).qout + ai.nin);
+        ns = std::max(ns, kind_form(ao.bwd).pin + ao.nin);
+      }
+      p->ax[a].nspec = ns;
     }
-    p->ax[swap_axis].nspec = ns;
   }
   if (p->kind != FM_POISSON) {
     if (p->ncomp != 3) return FM_E_KIND;
     for (int a = 0; a < 3; ++a)
-      if (!p->ax[a].dft && a != swap_axis) return FM_E_KIND;
+      if (!p->ax[a].dft && !swap[a]) return FM_E_KIND;
   }
   // transform order: symmetric < semi-unbounded < periodic < unbounded (cost)
   auto cost = [](int c) {
@@ -1113,7 +1139,11 @@ int build_plan(fm_plan_s* p) {
   bool seen_dft = false;
   for (int i = 0; i < 3; ++i) {
     AxisPlan& a = p->ax[ord[i]];
-    if (a.dft && !seen_dft) { a.first_dft = true; seen_dft = true; }
+    // with two symmetric axes of a vector plan the DFT axis is a full complex DFT (the
+    // curl mixes the components line by line, which two real lines packed in one complex
+    // FFT would not allow)
+    if (a.dft && !seen_dft && !p->vec2) a.first_dft = true;
+    if (a.dft) seen_dft = true;
     if (a.dft) a.nspec = a.first_dft ? a.M / 2 + 1 : a.M;
   }
   // Green table geometry per axis
@@ -1137,8 +1167,9 @@ int build_plan(fm_plan_s* p) {
       a.off = f.qout;      // spectral index s pairs with kernel mode s + qout
     }
   }
-  if (swap_axis >= 0) {  // frequency-indexed spectrum along the swap axis
-    AxisPlan& a = p->ax[swap_axis];
+  for (int sa = 0; sa < 3; ++sa) {  // frequency-indexed spectra along the swap axes
+    if (!swap[sa]) continue;
+    AxisPlan& a = p->ax[sa];
     if (a.unb) a.off = 0;
     else a.shift = 0.5 * kind_form(a.fwd).b2;
   }
@@ -1169,7 +1200,7 @@ int build_plan(fm_plan_s* p) {
   layout_strides(p->L1, p->ext1, s1, &p->V1);
   layout_strides(p->L2, p->ext2, s2, &p->V2);
   p->cplx1 = p->ax[a0].dft;
-  p->cplx2 = p->ax[a0].dft || p->ax[a1].dft;
+  p->cplx2 = p->ax[a0].dft || p->ax[a1].dft || p->vec2;
   p->elem = (p->prec == FM_F64) ? 8 : 4;
   p->bytesA = round256(p->V1 * p->elem * (p->cplx1 ? 2 : 1));
   p->bytesB = round256(p->V2 * p->elem * (p->cplx2 ? 2 : 1));
@@ -1201,9 +1232,16 @@ int build_plan(fm_plan_s* p) {
     set_geometry(&d, a1, a2, a0, s1, p->V1, s2, p->V2, p->ext1);
     set_transform(&d, p->ax[a1], true, false);
     d.in_cplx = p->cplx1;
-    d.out_cplx = p->cplx2;
+    d.out_cplx = p->cplx2;  // a second symmetric axis: complex values, zero imaginary part
     d.in_n = wext[a1];
     d.out_n = p->ax[a1].nspec;
+    if (p->vec2) {
+      for (int q = 0; q < 3; ++q) {
+        p->vr2r[q][2] = make_r2r(vin[q][a1], vin[q][a1].fwd, true, true);
+        p->vr2r[q][3] = make_r2r(vout[q][a1], vout[q][a1].bwd, false, true);
+      }
+      d.r2r = p->vr2r[0][2];
+    }
   }
   // pass 3: fused along a2 in L2, tiles along a1
   {
@@ -1254,6 +1292,10 @@ int build_plan(fm_plan_s* p) {
       // axis (Sec. V)
       const AxisPlan& ai = vin[(a0 + 1) % 3][a0];
       g.csym = ((ai.fwd >= RODFT00) != ai.rev) ? 1 : -1;
+      if (p->vec2) {  // the same along the second symmetric axis (a1, direction b)
+        const AxisPlan& bi = vin[(a1 + 1) % 3][a1];
+        g.csym_b = ((bi.fwd >= RODFT00) != bi.rev) ? 1 : -1;
+      }
     }
   }
   // pass 4: L2 -> L1 along a1 (inverse of pass 2)
@@ -1266,6 +1308,15 @@ int build_plan(fm_plan_s* p) {
     d.out_cplx = p->cplx1;
     d.in_n = p->ax[a1].nspec;
     d.out_n = wext[a1];
+    if (p->vec2) {
+      // the real parts of the complex values of the fused pass (their imaginary parts
+      // are the rounding of a real result): real elements at twice the complex strides
+      d.in_cplx = 0;
+      d.in_s_line *= 2;
+      d.in_s_b *= 2;
+      d.in_s_c *= 2;
+      d.r2r = p->vr2r[0][3];
+    }
   }
   // pass 5: L1 -> user along a0 (inverse of pass 1)
   {
@@ -1288,6 +1339,19 @@ int build_plan(fm_plan_s* p) {
     fix_axis(p->ax[o1], &d.fix.c_dup, &d.fix.c_zero_lo, &d.fix.c_zero_hi, &d.fix.c_last);
     d.has_fix = d.fix.b_dup | d.fix.b_zero_lo | d.fix.b_zero_hi | d.fix.c_dup | d.fix.c_zero_lo |
                 d.fix.c_zero_hi;
+    if (p->vec) {
+      // each component's own faces (its velocity faces on a second symmetric axis, which
+      // is a batch axis of this pass): packed real lines leave rounding on a zero line, so
+      // the odd-face nodes are zeroed here
+      for (int q = 0; q < 3; ++q) {
+        fm::Fixup& fx = p->vfix[q];
+        fix_axis(vout[q][p->tb1], &fx.b_dup, &fx.b_zero_lo, &fx.b_zero_hi, &fx.b_last);
+        fix_axis(vout[q][o1], &fx.c_dup, &fx.c_zero_lo, &fx.c_zero_hi, &fx.c_last);
+        p->vhas_fix[q] = fx.b_dup | fx.b_zero_lo | fx.b_zero_hi | fx.c_dup | fx.c_zero_lo | fx.c_zero_hi;
+      }
+      d.fix = p->vfix[0];
+      d.has_fix = p->vhas_fix[0];
+    }
   }
   // component strides of the work buffers (elements), fixed by the plan
   {
@@ -1298,7 +1362,7 @@ int build_plan(fm_plan_s* p) {
     p->pass[1].out_s_comp = compB;
     p->pass[2].in_s_comp = compB;
     p->pass[2].out_s_comp = compB;
-    p->pass[3].in_s_comp = compB;
+    p->pass[3].in_s_comp = p->vec2 ? 2 * compB : compB;
     p->pass[3].out_s_comp = compA;
     p->pass[4].in_s_comp = compA;
   }
@@ -1339,7 +1403,7 @@ int build_plan(fm_plan_s* p) {
     const int rc = radix_plan(p->ax[line_axis[i]].M, &d);
     if (rc) return rc;
     const bool fused_curl = (i == 2) && curl;
-    d.ncomp = (p->vec && (i == 0 || i == 4)) ? 1 : p->ncomp;  // launched per component
+    d.ncomp = vec_pass(p, i) ? 1 : p->ncomp;  // launched per component
     d.long_rt = 0;
     d.persist = 1;
     d.lds_tabs = 1;
@@ -1367,7 +1431,8 @@ int build_plan(fm_plan_s* p) {
     }
   }
   for (int i = 0; i < fm_plan_s::kPasses; ++i) p->pass[i].kind = pass_kind(p->pass[i]);
-  const int64_t sizes_in[fm_plan_s::kPasses] = {p->Vu, p->V1, p->V2, p->V2, p->V1, p->V2, p->Vspec};
+  const int64_t sizes_in[fm_plan_s::kPasses] = {p->Vu, p->V1, p->V2, p->vec2 ? 2 * p->V2 : p->V2, p->V1,
+                                                p->V2, p->Vspec};
   const int64_t sizes_out[fm_plan_s::kPasses] = {p->V1, p->V2, p->V2, p->V1, p->Vu, p->Vspec, p->V2};
   for (int i = 0; i < fm_plan_s::kPasses; ++i)
     if (!pass_in_bounds(p->pass[i], sizes_in[i], sizes_out[i], p->elem)) return FM_E_SIZE;
@@ -1413,7 +1478,7 @@ int launch_one(fm_plan_s* p, int i, const void* in, void* out, hipStream_t st) {
                                : fm::launch_pass<float>(dq, dev, iq, oq, st);
   };
   hipError_t e = run(d, p->dpass + i, in, out);
-  if (p->vec && (i == 0 || i == 4)) {
+  if (vec_pass(p, i)) {
     // the other two components, each with its own transform along the swap axis
     const size_t es_in = p->elem * (d.in_cplx ? 2 : 1), es_out = p->elem * (d.out_cplx ? 2 : 1);
     for (int q = 1; q < 3 && e == hipSuccess; ++q) {
@@ -1977,7 +2042,7 @@ int launch_mode(const fm::PassDesc& d, size_t elem) {
 bool retile(const fm_plan_s* p, int i, int bmax, int mode, fm::PassDesc* out) {
   fm::PassDesc d = p->pass[i];
   const bool fused_curl = (i == 2) && p->kind != FM_POISSON;
-  const int64_t sizes_in[5] = {p->Vu, p->V1, p->V2, p->V2, p->V1};
+  const int64_t sizes_in[5] = {p->Vu, p->V1, p->V2, p->vec2 ? 2 * p->V2 : p->V2, p->V1};
   const int64_t sizes_out[5] = {p->V1, p->V2, p->V2, p->V1, p->Vu};
   d.wave = 0;
   // the per-wavefront kernel has the compile-time length; the LDS-tile kernel takes the

@@ -148,16 +148,16 @@ __device__ __forceinline__ void wave_tile(const PassDesc& d, const void* in, voi
   if constexpr (KIND == K_F_CURL) {
 #pragma unroll
     for (int m = 0; m < E; ++m) g[m] = G[grow + fold_index(j + P * m, d.g.fold_line)];
-    T wc, mc;
-    curl_c_factor<T>(d.g, curl_wave<T>(ti.c, d.g.dtab_c), wc, mc);
-    const T wb = curl_wave<T>(b, d.g.dtab_b);
+    T wc, mc, wb, mb;
+    curl_factor<T>(d.g.csym, curl_wave<T>(ti.c, d.g.dtab_c), wc, mc);
+    curl_factor<T>(d.g.csym_b, curl_wave<T>(b, d.g.dtab_b), wb, mb);
 #pragma unroll
     for (int m = 0; m < E; ++m) {
       const T wl = curl_wave<T>(j + P * m, d.g.dtab_line);
       const T wx = d.g.axis_line == 0 ? wl : (d.g.axis_b == 0 ? wb : wc);
       const T wy = d.g.axis_line == 1 ? wl : (d.g.axis_b == 1 ? wb : wc);
       const T wz = d.g.axis_line == 2 ? wl : (d.g.axis_b == 2 ? wb : wc);
-      curl_point<T>(g[m], wx, wy, wz, d.g.axis_c, mc, v[0][m], v[1][m], v[2][m]);
+      curl_point<T>(g[m], wx, wy, wz, d.g.axis_c, mc, d.g.axis_b, mb, v[0][m], v[1][m], v[2][m]);
     }
   } else {
 #pragma unroll

@@ -4,7 +4,7 @@ derivative swaps DCT and DST), against the oracle's per-component solve, element
 element, in both precisions and layouts, the default and the tuned tilings, spectral and
 finite-difference curls; the output conventions of each component's swapped faces; the
 vortex-tube validation of Sec. V (x, y unbounded, z symmetric) converging at second
-order; the refusals."""
+order; two symmetric axes; the refusals."""
 import numpy as np
 import pytest
 
@@ -190,10 +190,10 @@ def test_vortex_tube_parity_and_order():
 def test_vector_refusals():
     import torch
     h = [0.1] * 3
-    # two symmetric axes: not built on the GPU
-    two = [[[OD, OD], [E, E], [U, U]], [[E, E], [OD, OD], [U, U]], [[E, E], [E, E], [U, U]]]
+    # three symmetric axes: not built on the GPU
+    three = faces_multi({0: (E, E), 1: (E, E), 2: (OD, OD)}, {})
     with pytest.raises(F.FluxmiError) as e:
-        F.Plan([8, 8, 8], h, two, F.CELL, F.CHAT2, F.F64, F.BIOT_SAVART)
+        F.Plan([8, 8, 8], h, three, F.CELL, F.CHAT2, F.F64, F.BIOT_SAVART)
     assert e.value.status == -4
     # faces that are not those of a mirror-symmetric field
     bad = [[[E, E], [U, U], [U, U]]] * 3
@@ -234,4 +234,45 @@ def test_vector_regularised_kernels(green, layout):
         ref = O.solve_vector(f, n, h, bcv, layout, green, F.BIOT_SAVART)
         plan = F.Plan(n, h, bcv, layout, green, F.F64, F.BIOT_SAVART)
         _run(plan, f, ref, TOL64, O.swap_faces(bcv), layout, (green, axis))
+        plan.close()
+
+
+def faces_multi(sym, other):
+    """Faces per component with several symmetric axes: sym = {axis: tangential faces},
+    the component along each such axis gets them swapped; `other` on the other axes."""
+    out = []
+    for q in range(3):
+        comp = []
+        for a in range(3):
+            if a in sym:
+                comp.append([SW[b] for b in sym[a]] if q == a else list(sym[a]))
+            else:
+                comp.append(list(other[a]))
+        out.append(comp)
+    return out
+
+
+# two symmetric / semi-unbounded axes (passes 1, 2, 4 and 5 per component; the DFT axis
+# transformed as a full complex DFT)
+CASES2 = [
+    ([16, 15, 18], [0.06, 0.07, 0.05], {0: (E, E), 1: (E, OD)}, {2: (U, U)}, F.CELL),
+    ([16, 18, 14], [0.06, 0.05, 0.07], {0: (OD, OD), 2: (E, U)}, {1: (P, P)}, F.NODE),
+    ([15, 16, 18], [0.07, 0.06, 0.05], {1: (U, E), 2: (OD, OD)}, {0: (U, U)}, F.CELL),
+    ([18, 16, 16], [0.05, 0.06, 0.06], {0: (OD, E), 1: (U, OD)}, {2: (P, P)}, F.NODE),
+]
+
+
+@pytest.mark.parametrize("prec,tol", [(F.F64, TOL64), (F.F32, TOL32)])
+@pytest.mark.parametrize("case", range(len(CASES2)))
+def test_vector_two_symmetric_axes(case, prec, tol):
+    n, h, sym, other, layout = CASES2[case]
+    bcv = faces_multi(sym, other)
+    f = np.random.default_rng(200 + case).standard_normal((3,) + O.user_shape(n, layout))
+    out_faces = O.swap_faces(bcv)
+    for kind in (F.BIOT_SAVART, F.BIOT_SAVART_FD2):
+        ref = O.solve_vector(f, n, h, bcv, layout, 0, kind)
+        plan = F.Plan(n, h, bcv, layout, F.CHAT2, prec, kind)
+        _run(plan, f, ref, tol, out_faces, layout, (case, kind, "default"))
+        plan.tune()
+        _run(plan, f, ref, tol, out_faces, layout, (case, kind, "tuned", plan.tiling()))
         plan.close()
