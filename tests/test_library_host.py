@@ -115,3 +115,39 @@ def test_biot_savart_512_plans_in_both_precisions():
         info = F.plan_inspect([512] * 3, [2 / 512] * 3, [[3, 3]] * 3, 0, F.CHAT2, prec, F.BIOT_SAVART, 3)
         assert info["fft_len"] == [1024] * 3
         assert 1 <= info["lines_per_tile"][2] <= 64
+
+
+def _create_vector(n, h, bcv, layout=0, kind=1, prec=0):
+    """fm_plan_create_vector's status on the host (no device: a problem that passes
+    planning fails afterwards with FM_E_HIP and leaves no plan)."""
+    import ctypes
+    lib = F.library()
+    n3 = (ctypes.c_int * 3)(*n)
+    h3 = (ctypes.c_double * 3)(*h)
+    b18 = (ctypes.c_int * 18)(*[int(v) for c in bcv for f in c for v in f])
+    handle = ctypes.c_void_p()
+    rc = lib.fm_plan_create_vector(ctypes.byref(handle), n3, h3, b18, layout, 0, prec, kind, None)
+    assert handle.value is None or rc == 0
+    return rc
+
+
+def test_vector_plan_faces_checked_before_the_device():
+    """Faces per component: a mirror-symmetric set with one or two symmetric axes plans
+    (and then needs the device), one that is not mirror-symmetric is FM_E_BC, three
+    symmetric axes and the Poisson kind are FM_E_KIND."""
+    n, h = [8, 8, 8], [0.1] * 3
+    U, E, OD, P = 3, 0, 1, 2
+    one = [[[OD, OD], [U, U], [U, U]], [[E, E], [U, U], [U, U]], [[E, E], [U, U], [U, U]]]
+    two = [[[OD, OD], [E, U], [P, P]], [[E, E], [OD, U], [P, P]], [[E, E], [E, U], [P, P]]]
+    three = [[[OD, OD], [E, E], [E, E]], [[E, E], [OD, OD], [E, E]], [[E, E], [E, E], [OD, OD]]]
+    for layout in (0, 1):
+        for prec in (0, 1):
+            assert _create_vector(n, h, one, layout, prec=prec) == -6   # planned; no device
+            assert _create_vector(n, h, two, layout, prec=prec) == -6
+    assert _create_vector(n, h, three) == -4
+    assert _create_vector(n, h, one, kind=0) == -4
+    bad = [c[:] for c in one]
+    bad[0] = [[E, E], [U, U], [U, U]]            # normal component with the tangential symmetry
+    assert _create_vector(n, h, bad) == -2
+    mixed = [[[U, U]] * 3, [[P, P], [U, U], [U, U]], [[U, U]] * 3]   # periodic and unbounded mixed
+    assert _create_vector(n, h, mixed) == -2
