@@ -443,7 +443,8 @@ int choose_tile(fm::PassDesc* d, size_t elem, int comps, bool fused_r2r, int nb,
 // The per-wavefront fused kernel (fm_wave.h) with E values per lane: complex fused
 // passes of a power-of-two length whose lines are contiguous in memory (every fused
 // complex pass: the last axis is the fastest of its layout); three-component lines of 16
-// values per lane in FP64 only at 1024 points (one line per wavefront).
+// values per lane in FP64 only at 1024 points (one line per wavefront) and without a
+// second symmetric axis.
 int wave_plain_rs(const fm::PassDesc& d, int E);
 
 bool wave_capable(const fm::PassDesc& d, size_t elem, int E) {
@@ -453,7 +454,7 @@ bool wave_capable(const fm::PassDesc& d, size_t elem, int E) {
   if (!d.fused && d.gather == fm::G_R2R && d.out_cplx) return false;  // LDS-tile kernel only
   if (!d.fused) return wave_plain_rs(d, E) > 0;
   if (d.gather != fm::G_CPLX) return false;
-  if (d.g.curl && elem != 4 && E == 16 && d.M != 1024) return false;
+  if (d.g.curl && elem != 4 && E == 16 && (d.M != 1024 || d.g.csym_b != 0)) return false;
   return d.in_s_line == 1 && d.out_s_line == 1;
 }
 

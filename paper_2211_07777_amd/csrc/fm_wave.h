@@ -150,7 +150,14 @@ __device__ __forceinline__ void wave_tile(const PassDesc& d, const void* in, voi
     for (int m = 0; m < E; ++m) g[m] = G[grow + fold_index(j + P * m, d.g.fold_line)];
     T wc, mc, wb, mb;
     curl_factor<T>(d.g.csym, curl_wave<T>(ti.c, d.g.dtab_c), wc, mc);
-    curl_factor<T>(d.g.csym_b, curl_wave<T>(b, d.g.dtab_b), wb, mb);
+    if constexpr (sizeof(T) == 8 && E == 16) {
+      // no symmetric b direction in this instance (its registers are full; the planner
+      // keeps such passes off it)
+      wb = curl_wave<T>(b, d.g.dtab_b);
+      mb = T(0);
+    } else {
+      curl_factor<T>(d.g.csym_b, curl_wave<T>(b, d.g.dtab_b), wb, mb);
+    }
 #pragma unroll
     for (int m = 0; m < E; ++m) {
       const T wl = curl_wave<T>(j + P * m, d.g.dtab_line);
