@@ -137,9 +137,9 @@ int fm_plan_create(fm_plan* out, const int n[3], const double h[3], const int bc
  * turns even into odd and odd into even, so component p of the solution has the faces of
  * component p of f with even and odd swapped; in spectral space the derivative of a sine
  * coefficient is +w times it and that of a cosine coefficient -w times it (Sec. V).
- * One or two axes may be symmetric or semi-unbounded (Sec. II-B, II-C), the others
- * periodic or unbounded (three symmetric axes: FM_E_KIND); without a symmetric face the
- * plan is fm_plan_create's Biot-Savart plan.  kind: FM_BIOT_SAVART or one of its _FD forms; the other arguments,
+ * Any number of axes may be symmetric or semi-unbounded (Sec. II-B, II-C), the others
+ * periodic or unbounded; without a symmetric face the plan is fm_plan_create's
+ * Biot-Savart plan.  kind: FM_BIOT_SAVART or one of its _FD forms; the other arguments,
  * the ownership and the solve calls as for fm_plan_create with ncomp = 3.  Such a plan
  * is solved one request at a time: fm_solve_batched, fm_batch_prepare, fm_fft_forward
  * and fm_fft_backward return FM_E_KIND for it.

@@ -2,6 +2,8 @@
 // pass launchers.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "fm_device.h"
 #include "fm_launch.h"
 #include "fm_special.h"
@@ -347,6 +349,41 @@ hipError_t launch_green_final(void* G, const double* S, const int F[3], const in
   return hipGetLastError();
 }
 
+// u_hat_p = G sum over (a, b) of eps_pab s_ab w_a psi_hat_b at every point of the real
+// spectra (all three axes symmetric: every derivative is a real factor, Sec. V).
+template <typename T>
+__global__ void curl_real_kernel(CurlReal c) {
+  const int64_t total = (int64_t)c.n[0] * c.n[1] * c.n[2];
+  T* S = reinterpret_cast<T*>(c.S);
+  const T* G = reinterpret_cast<const T*>(c.G);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i2 = i % c.n[2], r = i / c.n[2];
+    const int64_t i1 = r % c.n[1], i0 = r / c.n[1];
+    T w[3];  // derivative factor along physical axes x, y, z
+    w[c.ax[0]] = reinterpret_cast<const T*>(c.d[0])[i0];
+    w[c.ax[1]] = reinterpret_cast<const T*>(c.d[1])[i1];
+    w[c.ax[2]] = reinterpret_cast<const T*>(c.d[2])[i2];
+    const T f[3] = {S[i], S[i + c.comp_stride], S[i + 2 * c.comp_stride]};
+    auto D = [&](int a, int b) { return T(c.sg[a][b]) * w[a] * f[b]; };  // d/dx_a of component b
+    const T g = G[i];
+    const T ux = D(1, 2) - D(2, 1), uy = D(2, 0) - D(0, 2), uz = D(0, 1) - D(1, 0);
+    S[i] = g * ux;
+    S[i + c.comp_stride] = g * uy;
+    S[i + 2 * c.comp_stride] = g * uz;
+  }
+}
+
+template <typename T>
+hipError_t launch_curl_real(const CurlReal& c, hipStream_t st) {
+  const int64_t total = (int64_t)c.n[0] * c.n[1] * c.n[2];
+  const int64_t blocks = std::min<int64_t>((total + 255) / 256, 4096);
+  hipLaunchKernelGGL(curl_real_kernel<T>, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, c);
+  return hipGetLastError();
+}
+
+template hipError_t launch_curl_real<float>(const CurlReal&, hipStream_t);
+template hipError_t launch_curl_real<double>(const CurlReal&, hipStream_t);
 template hipError_t launch_pass<float>(const PassDesc&, const PassDesc*, const void*, void*, hipStream_t);
 template hipError_t launch_pass<double>(const PassDesc&, const PassDesc*, const void*, void*, hipStream_t);
 template hipError_t launch_pass_batched<float>(int, const PassDesc*, const int*, int, int, int, hipStream_t);

@@ -282,6 +282,23 @@ struct GreenGen {
   double eps, kc;            // regularised kernels: smoothing length, spectral cut-off
 };
 
+// Biot-Savart with three symmetric axes (conditions per component): the curl times the
+// Green's spectrum on the real three-axis spectra of the components, in place.  Spectra
+// [comp][n0][n1][n2] (table axes a0 slowest .. a2 fastest, frequency-indexed), Green's
+// table of the same extents; d[t] the derivative factor of each frequency of table axis t;
+// ax[t] its physical axis; sg[a][b] the sign of the derivative of component b along
+// physical axis a (+1 after a sine transform, -1 after a cosine one, flipped on a
+// reversed axis).
+struct CurlReal {
+  void* S;                   // spectra, working precision
+  int64_t comp_stride;       // elements between components
+  const void* G;             // Green's table
+  const void* d[3];          // derivative factors per table axis
+  int32_t n[3];              // extents per table axis
+  int32_t ax[3];             // physical axis of each table axis
+  int32_t sg[3][3];          // [physical axis][component]
+};
+
 // Lattice Green's function (LGF2) quadrature: nodes t_k = exp(u_lo + k du), k < K, and
 // per table axis the scaled Bessel values exp(-x) I_n(x), x = 2 t_k / h^2, n < nA.
 struct LgfGen {

@@ -34,6 +34,8 @@ bool is_fast_len(int M);
 hipError_t launch_green_sample(double* S, const GreenGen& g, hipStream_t st);
 hipError_t launch_lgf(double* S, double* A, double* W, const LgfGen& g, hipStream_t st);
 template <typename T>
+hipError_t launch_curl_real(const CurlReal& c, hipStream_t st);
+template <typename T>
 hipError_t launch_green_final(void* G, const double* S, const int F[3], const int n[3],
                               const int off[3], double scale, hipStream_t st);
 }  // namespace fm
@@ -288,12 +290,18 @@ struct fm_plan_s {
   // DFT axis is then transformed as a full complex DFT, pass 2 writes complex values with
   // a zero imaginary part and pass 4 reads their real parts
   bool vec2 = false;
+  // three symmetric axes: pass 3 is replaced by the plain transforms along the last axis
+  // (descriptors 6 and 7, once per component) around the real curl on the spectra in a
+  // workspace region after B (curl_real_kernel)
+  bool vec3 = false;
+  fm::CurlReal vcurl{};
   int bcv[3][3][2] = {};
-  // [component][0: pass 1 forward, 1: pass 5 backward, 2: pass 2 forward, 3: pass 4 backward]
-  fm::R2R vr2r[3][4] = {};
+  // [component][0: pass 1 forward, 1: pass 5 backward, 2: pass 2 forward, 3: pass 4
+  // backward, 4: last-axis forward, 5: last-axis backward]
+  fm::R2R vr2r[3][6] = {};
   fm::Fixup vfix[3] = {};  // pass 5's output conventions per component (its faces)
   int vhas_fix[3] = {};
-  static constexpr int kVecDesc = 8;
+  static constexpr int kVecDesc = 12;
   fm::PassDesc vdesc[kVecDesc];  // host copies of the device slots (vec_slot)
 };
 
@@ -599,10 +607,11 @@ void release_generation(fm_plan_s* p) {
 // Whether pass i of a plan runs once per component (vector plans: passes 1 and 5, and 2
 // and 4 with a second symmetric axis).
 bool vec_pass(const fm_plan_s* p, int i) {
-  return p->vec && (i == 0 || i == 4 || (p->vec2 && (i == 1 || i == 3)));
+  return p->vec && (i == 0 || i == 4 || ((p->vec2 || p->vec3) && (i == 1 || i == 3)) ||
+                    (p->vec3 && (i == 5 || i == 6)));
 }
 // Per-component transform of pass i (vr2r's second index).
-int vec_r2r(int i) { return i == 0 ? 0 : (i == 4 ? 1 : (i == 1 ? 2 : 3)); }
+int vec_r2r(int i) { return i == 0 ? 0 : i == 4 ? 1 : i == 1 ? 2 : i == 3 ? 3 : i == 5 ? 4 : 5; }
 // Device slot, after the kPasses, of component q (1 or 2) of pass i of a vector plan.
 int vec_slot(int i, int q) { return 2 * vec_r2r(i) + (q - 1); }
 
@@ -610,7 +619,7 @@ int vec_slot(int i, int q) { return 2 * vec_r2r(i) + (q - 1); }
 // rebuilt from the plan's (component 0) descriptors with their own transforms, and
 // uploaded.
 hipError_t upload_vec_descs(fm_plan_s* p, hipStream_t st) {
-  for (const int i : {0, 1, 3, 4}) {
+  for (const int i : {0, 1, 3, 4, 5, 6}) {
     if (!vec_pass(p, i)) continue;
     for (int q = 1; q < 3; ++q) {
       fm::PassDesc& d = p->vdesc[vec_slot(i, q)];
@@ -691,7 +700,7 @@ int make_tables_and_green(fm_plan_s* p, hipStream_t st, bool deferred) {
   // the curl's derivative factor of every DFT mode k (signed k_s) of the three directions
   // of the fused pass, in FP64, rounded once: the wavenumber 2 pi k_s / period (0 at the
   // Nyquist mode), or the central-difference symbol (1/h) sum_j c_j sin(2 pi j k_s / M)
-  if (p->pass[2].g.curl) {
+  if (p->pass[2].g.curl || p->vec3) {
     fm::GreenRef& g = p->pass[2].g;
     const int order = g.deriv;
     const int axes[3] = {g.axis_line, g.axis_b, g.axis_c};
@@ -879,6 +888,13 @@ int make_tables_and_green(fm_plan_s* p, hipStream_t st, bool deferred) {
   }
   // the pass descriptors, now complete, go to device memory
   for (int i = 0; i < fm_plan_s::kPasses; ++i) p->pass[i].g.G = p->G;
+  if (p->vec3) {  // the real curl reads the same Green's table and derivative tables
+    const fm::GreenRef& g = p->pass[2].g;
+    p->vcurl.G = p->G;
+    p->vcurl.d[0] = g.dtab_c;     // table axis a0 = direction c of pass 3
+    p->vcurl.d[1] = g.dtab_b;
+    p->vcurl.d[2] = g.dtab_line;
+  }
   if (rc == FM_OK) {
     const size_t nb = sizeof(fm::PassDesc) * fm_plan_s::kPasses;
     const size_t nv = p->vec ? sizeof(fm::PassDesc) * fm_plan_s::kVecDesc : 0;
@@ -1107,8 +1123,9 @@ int build_plan(fm_plan_s* p) {
         swap[a] = true;
         ++nswap;
       }
-    if (nswap == 0 || nswap == 3) return FM_E_KIND;
+    if (nswap == 0) return FM_E_KIND;
     p->vec2 = nswap == 2;
+    p->vec3 = nswap == 3;
     // spectral extent along each: every frequency index of the components' kinds
     for (int a = 0; a < 3; ++a) {
       if (!swap[a]) continue;
@@ -1236,7 +1253,7 @@ int build_plan(fm_plan_s* p) {
     d.out_cplx = p->cplx2;  // a second symmetric axis: complex values, zero imaginary part
     d.in_n = wext[a1];
     d.out_n = p->ax[a1].nspec;
-    if (p->vec2) {
+    if (p->vec2 || p->vec3) {
       for (int q = 0; q < 3; ++q) {
         p->vr2r[q][2] = make_r2r(vin[q][a1], vin[q][a1].fwd, true, true);
         p->vr2r[q][3] = make_r2r(vout[q][a1], vout[q][a1].bwd, false, true);
@@ -1274,7 +1291,7 @@ int build_plan(fm_plan_s* p) {
     g.fold_c = p->ax[a0].dft ? p->ax[a0].M : 0;
     g.fold_b = p->ax[a1].dft ? p->ax[a1].M : 0;
     g.fold_line = A.dft ? A.M : 0;
-    g.curl = curl ? 1 : 0;
+    g.curl = (curl && !p->vec3) ? 1 : 0;  // three symmetric axes: not launched (curl_real_kernel)
     g.axis_line = a2;
     g.axis_b = a1;
     g.axis_c = a0;
@@ -1309,6 +1326,7 @@ int build_plan(fm_plan_s* p) {
     d.out_cplx = p->cplx1;
     d.in_n = p->ax[a1].nspec;
     d.out_n = wext[a1];
+    if (p->vec3) d.r2r = p->vr2r[0][3];
     if (p->vec2) {
       // the real parts of the complex values of the fused pass (their imaginary parts
       // are the rounding of a real result): real elements at twice the complex strides
@@ -1397,13 +1415,36 @@ int build_plan(fm_plan_s* p) {
     f.out_s_comp = p->Vspec;
     g.in_s_comp = p->Vspec;
     g.out_s_comp = compB;
+    if (p->vec3) {
+      for (int q = 0; q < 3; ++q) {
+        p->vr2r[q][4] = make_r2r(vin[q][a2], vin[q][a2].fwd, true, true);
+        p->vr2r[q][5] = make_r2r(vout[q][a2], vout[q][a2].bwd, false, true);
+      }
+      f.r2r = p->vr2r[0][4];
+      g.r2r = p->vr2r[0][5];
+      // the spectra after B; the real curl's geometry (tables are set with the Green's
+      // spectrum)
+      p->ws_bytes += round256((size_t)3 * p->Vspec * p->elem);
+      fm::CurlReal& c = p->vcurl;
+      c.comp_stride = p->Vspec;
+      const int ta[3] = {a0, a1, a2};
+      for (int t = 0; t < 3; ++t) {
+        c.n[t] = p->ext_spec[ta[t]];
+        c.ax[t] = ta[t];
+      }
+      for (int a = 0; a < 3; ++a)
+        for (int q = 0; q < 3; ++q) {
+          const AxisPlan& ai = vin[q][a];
+          c.sg[a][q] = ((ai.fwd >= RODFT00) != ai.rev) ? 1 : -1;
+        }
+    }
   }
   const int line_axis[fm_plan_s::kPasses] = {a0, a1, a2, a1, a0, a2, a2};
   for (int i = 0; i < fm_plan_s::kPasses; ++i) {
     fm::PassDesc& d = p->pass[i];
     const int rc = radix_plan(p->ax[line_axis[i]].M, &d);
     if (rc) return rc;
-    const bool fused_curl = (i == 2) && curl;
+    const bool fused_curl = (i == 2) && curl && !p->vec3;
     d.ncomp = vec_pass(p, i) ? 1 : p->ncomp;  // launched per component
     d.long_rt = 0;
     d.persist = 1;
@@ -1497,10 +1538,28 @@ int launch_one(fm_plan_s* p, int i, const void* in, void* out, hipStream_t st) {
   return FM_OK;
 }
 
+// Pass 3 of a plan with three symmetric axes: the last axis's forward transform into the
+// spectra region after B, the real curl times the Green's spectrum there, the backward
+// transform into B (each transform once per component).
+int launch_curl3(fm_plan_s* p, void* B, hipStream_t st) {
+  char* S = static_cast<char*>(B) + (size_t)p->ncomp * p->bytesB;
+  int rc = launch_one(p, 5, B, S, st);
+  if (rc) return rc;
+  fm::CurlReal c = p->vcurl;
+  c.S = S;
+  const hipError_t e = (p->prec == FM_F64) ? fm::launch_curl_real<double>(c, st)
+                                           : fm::launch_curl_real<float>(c, st);
+  if (e != hipSuccess) {
+    g_last_hip = (int)e;
+    return FM_E_HIP;
+  }
+  return launch_one(p, 6, S, B, st);
+}
+
 int launch_all(fm_plan_s* p, const void* const ins[5], void* const outs[5], hipStream_t st,
                int first = 0, int last = 4) {
   for (int i = first; i <= last; ++i) {
-    const int rc = launch_one(p, i, ins[i], outs[i], st);
+    const int rc = (i == 2 && p->vec3) ? launch_curl3(p, outs[2], st) : launch_one(p, i, ins[i], outs[i], st);
     if (rc) return rc;
   }
   return FM_OK;
@@ -2234,6 +2293,7 @@ int fm_plan_tune(fm_plan p, void* workspace_dev, void* hip_stream) {
     return e;
   };
   for (int i = 0; i < 5 && he == hipSuccess; ++i) {
+    if (i == 2 && p->vec3) continue;  // not launched (the real curl replaces it)
     fm::PassDesc best = p->pass[i];
     float best_ms = 0.f;
     he = time_pass(i, best, &best_ms);

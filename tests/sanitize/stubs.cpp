@@ -23,6 +23,9 @@ hipError_t launch_green_final(void*, const double*, const int[3], const int[3], 
 }
 hipError_t launch_green_sample(double*, const GreenGen&, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_lgf(double*, double*, double*, const LgfGen&, hipStream_t) { return hipErrorNotSupported; }
+template <typename T> hipError_t launch_curl_real(const CurlReal&, hipStream_t) { return hipErrorNotSupported; }
+template hipError_t launch_curl_real<float>(const CurlReal&, hipStream_t);
+template hipError_t launch_curl_real<double>(const CurlReal&, hipStream_t);
 bool is_fast_len(int M) {
   for (int m : kFastLens)
     if (m == M) return true;

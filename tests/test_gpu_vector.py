@@ -4,7 +4,7 @@ derivative swaps DCT and DST), against the oracle's per-component solve, element
 element, in both precisions and layouts, the default and the tuned tilings, spectral and
 finite-difference curls; the output conventions of each component's swapped faces; the
 vortex-tube validation of Sec. V (x, y unbounded, z symmetric) converging at second
-order; two symmetric axes; the refusals."""
+order; two and three symmetric axes; the refusals."""
 import numpy as np
 import pytest
 
@@ -190,11 +190,6 @@ def test_vortex_tube_parity_and_order():
 def test_vector_refusals():
     import torch
     h = [0.1] * 3
-    # three symmetric axes: not built on the GPU
-    three = faces_multi({0: (E, E), 1: (E, E), 2: (OD, OD)}, {})
-    with pytest.raises(F.FluxmiError) as e:
-        F.Plan([8, 8, 8], h, three, F.CELL, F.CHAT2, F.F64, F.BIOT_SAVART)
-    assert e.value.status == -4
     # faces that are not those of a mirror-symmetric field
     bad = [[[E, E], [U, U], [U, U]]] * 3
     with pytest.raises(F.FluxmiError) as e:
@@ -275,4 +270,36 @@ def test_vector_two_symmetric_axes(case, prec, tol):
         _run(plan, f, ref, tol, out_faces, layout, (case, kind, "default"))
         plan.tune()
         _run(plan, f, ref, tol, out_faces, layout, (case, kind, "tuned", plan.tiling()))
+        plan.close()
+
+
+# three symmetric / semi-unbounded axes (pass 3 replaced by the last axis's transforms
+# around the real curl on the spectra)
+CASES3 = [
+    ([16, 15, 18], [0.06, 0.07, 0.05], {0: (E, E), 1: (E, OD), 2: (OD, OD)}, F.CELL),
+    ([16, 18, 14], [0.06, 0.05, 0.07], {0: (OD, OD), 1: (E, E), 2: (E, U)}, F.NODE),
+    ([15, 16, 18], [0.07, 0.06, 0.05], {0: (E, U), 1: (U, OD), 2: (E, E)}, F.CELL),
+    ([18, 16, 16], [0.05, 0.06, 0.06], {0: (OD, E), 1: (U, E), 2: (OD, OD)}, F.NODE),
+]
+
+
+@pytest.mark.parametrize("prec,tol", [(F.F64, TOL64), (F.F32, TOL32)])
+@pytest.mark.parametrize("case", range(len(CASES3)))
+def test_vector_three_symmetric_axes(case, prec, tol):
+    n, h, sym, layout = CASES3[case]
+    bcv = faces_multi(sym, {})
+    f = np.random.default_rng(300 + case).standard_normal((3,) + O.user_shape(n, layout))
+    out_faces = O.swap_faces(bcv)
+    for kind in (F.BIOT_SAVART, F.BIOT_SAVART_FD4):
+        ref = O.solve_vector(f, n, h, bcv, layout, 0, kind)
+        plan = F.Plan(n, h, bcv, layout, F.CHAT2, prec, kind)
+        _run(plan, f, ref, tol, out_faces, layout, (case, kind, "default"))
+        plan.tune()
+        _run(plan, f, ref, tol, out_faces, layout, (case, kind, "tuned", plan.tiling()))
+        import torch
+        x = torch.from_numpy(f).to("cuda", plan.dtype).contiguous()
+        out = torch.empty_like(x)
+        plan.solve_static(x, out)
+        torch.cuda.synchronize()
+        assert rel_linf(out.double().cpu().numpy(), ref) < tol
         plan.close()

@@ -132,9 +132,9 @@ def _create_vector(n, h, bcv, layout=0, kind=1, prec=0):
 
 
 def test_vector_plan_faces_checked_before_the_device():
-    """Faces per component: a mirror-symmetric set with one or two symmetric axes plans
-    (and then needs the device), one that is not mirror-symmetric is FM_E_BC, three
-    symmetric axes and the Poisson kind are FM_E_KIND."""
+    """Faces per component: a mirror-symmetric set with one, two or three symmetric axes
+    plans (and then needs the device), one that is not mirror-symmetric is FM_E_BC, the
+    Poisson kind is FM_E_KIND."""
     n, h = [8, 8, 8], [0.1] * 3
     U, E, OD, P = 3, 0, 1, 2
     one = [[[OD, OD], [U, U], [U, U]], [[E, E], [U, U], [U, U]], [[E, E], [U, U], [U, U]]]
@@ -144,7 +144,8 @@ def test_vector_plan_faces_checked_before_the_device():
         for prec in (0, 1):
             assert _create_vector(n, h, one, layout, prec=prec) == -6   # planned; no device
             assert _create_vector(n, h, two, layout, prec=prec) == -6
-    assert _create_vector(n, h, three) == -4
+    for layout in (0, 1):
+        assert _create_vector(n, h, three, layout) == -6
     assert _create_vector(n, h, one, kind=0) == -4
     bad = [c[:] for c in one]
     bad[0] = [[E, E], [U, U], [U, U]]            # normal component with the tangential symmetry
