@@ -1360,6 +1360,13 @@ __device__ __forceinline__ void run_pipelined(const PassDesc& d, const void* in,
   int k = 0;
   int tile = xcd_tile(blockIdx.x, gridDim.x, k, d.tiles);
   if (tile < 0) return;
+  // the first tile's input is requested before the tables are copied: the two HBM
+  // latencies overlap (the copy waits for both, loads completing in order)
+  RegStage<T, E, U * NCL> v;
+  GreenStage<T, UG> gs;
+  TileIdx ti = tile_index(d, tile);
+  fetch<U, NCL, false, E>(v, d, in, ti);
+  if constexpr (FUSED) fetch_green<T, UG>(gs, d, ti);
   // twiddle tables -> LDS (visible to the transform after the loop's barriers)
   cpx<T>* lt = reinterpret_cast<cpx<T>*>(smem + d.tab_off);
   {
@@ -1374,11 +1381,6 @@ __device__ __forceinline__ void run_pipelined(const PassDesc& d, const void* in,
   // real-to-real kinds always have their twiddles staged (tw_n = 2M); other kinds do
   // not read tw in the compile-time kernels
   const Tabs<const cpx<T>*> tb{lt, lt + d.stw_n};
-  RegStage<T, E, U * NCL> v;
-  GreenStage<T, UG> gs;
-  TileIdx ti = tile_index(d, tile);
-  fetch<U, NCL, false, E>(v, d, in, ti);
-  if constexpr (FUSED) fetch_green<T, UG>(gs, d, ti);
   while (true) {
     __syncthreads();  // the previous tile's LDS reads are finished
     commit<U, NCL, E>(v, d, ti, smem);

@@ -482,6 +482,11 @@ void wave_plain_kernel(const PassDesc* __restrict__ dp, const void* in, void* ou
   int tile = xcd_tile(blockIdx.x, gridDim.x, k, d.tiles);
   if (tile < 0) return;
   const bool lc_in = d.in_s_line == 1, lc_out = d.out_s_line == 1;
+  // the first tile's input is requested before the tables are copied, so that its HBM
+  // latency and the tables' overlap (the copy waits for both: loads complete in order)
+  TileIdx ti = tile_index(d, tile);
+  RegStage<T, In, WP::U> r;
+  wp_fetch<WP>(r, d, in, ti, lc_in);
   // tables into LDS, per-thread real-to-real gather weights
   cpx<T>* ltw = reinterpret_cast<cpx<T>*>(smem + d.tab_off);
   cpx<T>* lpost = ltw + WP::NTW;
@@ -505,9 +510,6 @@ void wave_plain_kernel(const PassDesc* __restrict__ dp, const void* in, void* ou
       slots[m] = sl;
     }
   }
-  TileIdx ti = tile_index(d, tile);
-  RegStage<T, In, WP::U> r;
-  wp_fetch<WP>(r, d, in, ti, lc_in);
   for (;;) {
     wp_commit<WP>(r, d, ti, smem, lc_in);
     __syncthreads();
