@@ -387,6 +387,16 @@ TileLds tile_lds(const fm::PassDesc& d, int B, size_t elem, int comps, bool fuse
   return t;
 }
 
+// FP32 one-launch batches and the FP32 fused real-to-real kernel of length 32 are off
+// in the library (an FP32 batched test faulted the GPU with no cause shown).  The CPU
+// emulation build of the device code (tests/emu) defines FM_FP32_ONE_LAUNCH to replay
+// those paths under the sanitizers.
+#ifdef FM_FP32_ONE_LAUNCH
+constexpr bool kFp32OneLaunch = true;
+#else
+constexpr bool kFp32OneLaunch = false;
+#endif
+
 // Kernel length class that fixes the values per thread of a pass.
 int pass_class(const fm::PassDesc& d) { return d.long_rt ? fm::kRtLong : d.M; }
 
@@ -396,7 +406,7 @@ int pass_class(const fm::PassDesc& d) { return d.long_rt ? fm::kRtLong : d.M; }
 // and nothing has shown it free of that fault.
 bool compile_time_kernel(const fm::PassDesc& d, size_t elem) {
   if (d.long_rt || !fm::is_fast_len(d.M)) return false;
-  if (elem == 4 && d.fused && d.gather == fm::G_R2R && d.M == 32) return false;
+  if (!kFp32OneLaunch && elem == 4 && d.fused && d.gather == fm::G_R2R && d.M == 32) return false;
   return true;
 }
 
@@ -1640,7 +1650,7 @@ int build_batch(int count, const fm_plan* plans, const void* const* rhs_dev, voi
     off += round256(plans[i]->ws_bytes);
   }
   host->clear();
-  if (prec == FM_F32) return FM_OK;  // plan by plan, no tables
+  if (prec == FM_F32 && !kFp32OneLaunch) return FM_OK;  // plan by plan, no tables
   std::vector<fm::PassDesc> all(5 * (size_t)count);
   for (int i = 0; i < count; ++i)
     for (int ps = 0; ps < 5; ++ps) {
@@ -1706,7 +1716,7 @@ int build_batch(int count, const fm_plan* plans, const void* const* rhs_dev, voi
 }
 
 int run_batch(const fm_batch_s& b, hipStream_t st) {
-  if (b.prec == FM_F32) {
+  if (b.prec == FM_F32 && !kFp32OneLaunch) {
     const size_t K = b.lanes.size();
     if (K == 0) {
       for (size_t i = 0; i < b.plans.size(); ++i) {
@@ -1736,9 +1746,11 @@ int run_batch(const fm_batch_s& b, hipStream_t st) {
     hipError_t e;
     if (g.single >= 0) {
       const fm::PassDesc& h = b.singles[g.single];
-      e = fm::launch_pass<double>(h, dd, h.in, h.out, st);
+      e = b.prec == FM_F32 ? fm::launch_pass<float>(h, dd, h.in, h.out, st)
+                           : fm::launch_pass<double>(h, dd, h.in, h.out, st);
     } else {
-      e = fm::launch_pass_batched<double>(g.len_class, dd, dp, g.count, g.tiles, g.lds, st);
+      e = b.prec == FM_F32 ? fm::launch_pass_batched<float>(g.len_class, dd, dp, g.count, g.tiles, g.lds, st)
+                           : fm::launch_pass_batched<double>(g.len_class, dd, dp, g.count, g.tiles, g.lds, st);
     }
     if (e != hipSuccess) {
       g_last_hip = (int)e;

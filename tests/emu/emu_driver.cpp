@@ -1,0 +1,190 @@
+// Replays solves on the CPU emulation of the device code (test infrastructure): each
+// case is planned and solved alone and compared with the FP64 oracle, then all cases of
+// one precision are solved again in one fm_solve_batched call and compared bitwise with
+// the single solves.  Each case is also solved in every launch mode its passes accept
+// (fm_plan_set_tiling) and with fm_solve_static, on a stream of its own.  Cases come from a text file, one per line:
+//   prec nx ny nz hx hy hz bx0 bx1 by0 by1 bz0 bz1 layout seed
+// Prints one line per case and exits non-zero on any failure.
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/fluxmi.h"
+
+extern "C" int oracle_solve(const int* n, const double* h, const int* bc, int layout, int green, int kind,
+                            int mode, const double* rhs, double* out);
+
+namespace {
+
+struct Case {
+  int prec, n[3], bc[3][2], layout;
+  double h[3];
+  unsigned seed;
+};
+
+// a reproducible field in [-1, 1) (64-bit LCG)
+void fill(std::vector<double>& v, unsigned seed) {
+  uint64_t s = 0x9e3779b97f4a7c15ull ^ seed;
+  for (double& x : v) {
+    s = s * 6364136223846793005ull + 1442695040888963407ull;
+    x = (double)(s >> 11) / (double)(1ull << 53) * 2.0 - 1.0;
+  }
+}
+
+double rel_linf(const std::vector<double>& a, const std::vector<double>& ref) {
+  double num = 0, den = 0;
+  for (size_t i = 0; i < a.size(); ++i) {
+    num = std::fmax(num, std::fabs(a[i] - ref[i]));
+    den = std::fmax(den, std::fabs(ref[i]));
+  }
+  return den > 0 ? num / den : num;
+}
+
+struct Run {
+  fm_plan plan = nullptr;
+  size_t count = 0, bytes = 0;
+  void* rhs = nullptr;
+  void* out = nullptr;
+  std::vector<double> f64;
+};
+
+}  // namespace
+
+int main(int argc, char** argv) {
+  if (argc < 2) {
+    std::fprintf(stderr, "usage: %s cases.txt\n", argv[0]);
+    return 2;
+  }
+  std::setvbuf(stdout, nullptr, _IOLBF, 0);
+  FILE* fh = std::fopen(argv[1], "r");
+  if (!fh) return 2;
+  std::vector<Case> cases;
+  Case c;
+  while (std::fscanf(fh, "%d %d %d %d %lf %lf %lf %d %d %d %d %d %d %d %u", &c.prec, &c.n[0], &c.n[1], &c.n[2],
+                     &c.h[0], &c.h[1], &c.h[2], &c.bc[0][0], &c.bc[0][1], &c.bc[1][0], &c.bc[1][1], &c.bc[2][0],
+                     &c.bc[2][1], &c.layout, &c.seed) == 15)
+    cases.push_back(c);
+  std::fclose(fh);
+  int failures = 0;
+  for (int prec : {FM_F64, FM_F32}) {
+    std::vector<Run> runs;
+    for (const Case& k : cases) {
+      if (k.prec != prec) continue;
+      Run r;
+      int rc = fm_plan_create(&r.plan, k.n, k.h, k.bc, k.layout, FM_GREEN_CHAT2, prec, FM_POISSON, 1, nullptr);
+      if (rc) {
+        std::printf("case n=%d,%d,%d plan failed: %s\n", k.n[0], k.n[1], k.n[2], fm_error_string(rc));
+        ++failures;
+        continue;
+      }
+      int dims[3];
+      fm_plan_shape(r.plan, dims);
+      r.count = (size_t)dims[0] * dims[1] * dims[2];
+      const size_t es = prec == FM_F64 ? 8 : 4;
+      r.bytes = r.count * es;
+      r.f64.resize(r.count);
+      fill(r.f64, k.seed);
+      r.rhs = std::malloc(r.bytes);
+      r.out = std::malloc(r.bytes);
+      for (size_t i = 0; i < r.count; ++i) {
+        if (es == 8) static_cast<double*>(r.rhs)[i] = r.f64[i];
+        else static_cast<float*>(r.rhs)[i] = (float)r.f64[i];
+      }
+      std::vector<double> fin(r.count), ref(r.count);
+      for (size_t i = 0; i < r.count; ++i) fin[i] = es == 8 ? r.f64[i] : (double)static_cast<float*>(r.rhs)[i];
+      const int orc = oracle_solve(k.n, k.h, &k.bc[0][0], k.layout, 0, 0, 0, fin.data(), ref.data());
+      const double tol = prec == FM_F64 ? 1e-12 : 1e-5;
+      auto check = [&](const char* what, int status, const void* out) {
+        std::vector<double> u(r.count);
+        for (size_t i = 0; i < r.count; ++i)
+          u[i] = es == 8 ? static_cast<const double*>(out)[i] : (double)static_cast<const float*>(out)[i];
+        const double err = (status || orc) ? INFINITY : rel_linf(u, ref);
+        const bool ok = err <= tol;
+        failures += !ok;
+        std::printf("%s %s n=%d,%d,%d bc=%d%d/%d%d/%d%d layout=%d: status %d rel_linf %.3e %s\n",
+                    prec == FM_F64 ? "FP64" : "FP32", what, k.n[0], k.n[1], k.n[2], k.bc[0][0], k.bc[0][1],
+                    k.bc[1][0], k.bc[1][1], k.bc[2][0], k.bc[2][1], k.layout, status, err, ok ? "ok" : "FAIL");
+      };
+      hipStream_t st = nullptr;
+      hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+      // every launch mode the passes accept, then the default tiling again
+      int lines0[5], tiles0[5], mode0[5];
+      fm_plan_tiling(r.plan, lines0, tiles0, mode0);
+      void* tmp = std::malloc(r.bytes);
+      for (int mode = 0; mode <= 5; ++mode) {
+        // each pass in this mode where the pass accepts it
+        // (with the first tile height of a short list that the pass takes in it)
+        int modes[5], lines[5], changed = 0;
+        for (int i = 0; i < 5; ++i) {
+          modes[i] = mode0[i];
+          lines[i] = lines0[i];
+        }
+        for (int i = 0; i < 5; ++i) {
+          if (modes[i] == mode) continue;
+          for (int b : {lines0[i], 1, 2, 4, 8, 16, 32, 64, 128, 256}) {
+            modes[i] = mode;
+            lines[i] = b;
+            if (fm_plan_set_tiling(r.plan, lines, modes, st) == FM_OK) {
+              ++changed;
+              break;
+            }
+            modes[i] = mode0[i];
+            lines[i] = lines0[i];
+          }
+        }
+        if (!changed || fm_plan_set_tiling(r.plan, lines, modes, st) != FM_OK) continue;
+        char what[32];
+        std::snprintf(what, sizeof(what), "mode %d", mode);
+        std::printf("  solving in mode %d (modes %d %d %d %d %d, lines %d %d %d %d %d)\n", mode, modes[0], modes[1],
+                    modes[2], modes[3], modes[4], lines[0], lines[1], lines[2], lines[3], lines[4]);
+        const int s1 = fm_solve(r.plan, r.rhs, tmp, nullptr, st);
+        hipStreamSynchronize(st);
+        check(what, s1, tmp);
+      }
+      rc = fm_plan_set_tiling(r.plan, lines0, mode0, st);
+      const int s2 = rc ? rc : fm_solve_static(r.plan, r.rhs, tmp, st);
+      hipStreamSynchronize(st);
+      check("static", s2, tmp);
+      std::free(tmp);
+      rc = fm_solve(r.plan, r.rhs, r.out, nullptr, st);
+      hipStreamSynchronize(st);
+      hipStreamDestroy(st);
+      check("single", rc, r.out);
+      runs.push_back(std::move(r));
+    }
+    if (runs.empty()) continue;
+    // the same plans in one batched call, compared bitwise with the single solves
+    std::vector<fm_plan> plans;
+    std::vector<const void*> ins;
+    std::vector<void*> outs;
+    for (Run& r : runs) {
+      plans.push_back(r.plan);
+      ins.push_back(r.rhs);
+      outs.push_back(std::malloc(r.bytes));
+    }
+    size_t wsb = 0;
+    int rc = fm_batched_workspace_bytes((int)plans.size(), plans.data(), &wsb);
+    void* ws = rc ? nullptr : std::malloc(wsb ? wsb : 1);
+    if (!rc) rc = fm_solve_batched((int)plans.size(), plans.data(), ins.data(), outs.data(), ws, wsb, nullptr);
+    hipDeviceSynchronize();
+    int same = 0;
+    for (size_t i = 0; i < runs.size(); ++i) same += !rc && std::memcmp(outs[i], runs[i].out, runs[i].bytes) == 0;
+    const bool ok = !rc && same == (int)runs.size();
+    failures += !ok;
+    std::printf("%s batched: %d plans, status %d, %d bitwise equal to single solves %s\n",
+                prec == FM_F64 ? "FP64" : "FP32", (int)runs.size(), rc, same, ok ? "ok" : "FAIL");
+    std::free(ws);
+    for (void* o : outs) std::free(o);
+    for (Run& r : runs) {
+      fm_plan_destroy(r.plan);
+      std::free(r.rhs);
+      std::free(r.out);
+    }
+  }
+  std::printf("emulated cases done, %d failure(s)\n", failures);
+  return failures ? 1 : 0;
+}
