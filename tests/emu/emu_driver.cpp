@@ -2,7 +2,9 @@
 // case is planned and solved alone and compared with the FP64 oracle, then all cases of
 // one precision are solved again in one fm_solve_batched call and compared bitwise with
 // the single solves.  Each case is also solved in every launch mode its passes accept
-// (fm_plan_set_tiling) and with fm_solve_static, on a stream of its own.  Cases come from a text file, one per line:
+// (fm_plan_set_tiling) and with fm_solve_static, on a stream of its own.  Finally
+// Biot-Savart plans with faces per component (one, two and three symmetric axes, the
+// spectral and a finite-difference curl) against the oracle's vector solve.  Cases come from a text file, one per line:
 //   prec nx ny nz hx hy hz bx0 bx1 by0 by1 bz0 bz1 layout seed
 // Prints one line per case and exits non-zero on any failure.
 #include <cmath>
@@ -17,6 +19,8 @@
 
 extern "C" int oracle_solve(const int* n, const double* h, const int* bc, int layout, int green, int kind,
                             int mode, const double* rhs, double* out);
+extern "C" int oracle_solve_vector(const int* n, const double* h, const int* bcv, int layout, int green,
+                                   int kind, int mode, const double* rhs, double* out);
 
 namespace {
 
@@ -185,6 +189,58 @@ int main(int argc, char** argv) {
       std::free(r.out);
     }
   }
+  // Biot-Savart with faces per component: axis a symmetric means component a even and
+  // the two others odd on its faces; the other axes unbounded
+  const int U = 3, E = 0, O = 1;
+  for (int prec : {FM_F64, FM_F32})
+    for (int nsym = 1; nsym <= 3; ++nsym)
+      for (int layout = 0; layout <= 1; ++layout) {
+        const int n[3] = {8, 6, 8};
+        const double h[3] = {0.1, 0.12, 0.09};
+        int bcv[3][3][2];
+        for (int q = 0; q < 3; ++q)
+          for (int a = 0; a < 3; ++a) {
+            const bool sym = a >= 3 - nsym;
+            bcv[q][a][0] = bcv[q][a][1] = sym ? (q == a ? E : O) : U;
+          }
+        const int kind = nsym == 2 ? FM_BIOT_SAVART_FD4 : FM_BIOT_SAVART;
+        fm_plan plan = nullptr;
+        int rc = fm_plan_create_vector(&plan, n, h, bcv, layout, FM_GREEN_CHAT2, prec, kind, nullptr);
+        if (rc) {
+          std::printf("vector plan failed: %s\n", fm_error_string(rc));
+          ++failures;
+          continue;
+        }
+        int dims[3];
+        fm_plan_shape(plan, dims);
+        const size_t count = 3 * (size_t)dims[0] * dims[1] * dims[2];
+        const size_t es = prec == FM_F64 ? 8 : 4;
+        std::vector<double> f(count), ref(count), u(count);
+        fill(f, 100 + nsym);
+        void* rhs = std::malloc(count * es);
+        void* out = std::malloc(count * es);
+        for (size_t i = 0; i < count; ++i) {
+          if (es == 8) static_cast<double*>(rhs)[i] = f[i];
+          else {
+            static_cast<float*>(rhs)[i] = (float)f[i];
+            f[i] = (double)static_cast<float*>(rhs)[i];
+          }
+        }
+        rc = fm_solve(plan, rhs, out, nullptr, nullptr);
+        hipDeviceSynchronize();
+        const int orc = oracle_solve_vector(n, h, &bcv[0][0][0], layout, 0, kind, 0, f.data(), ref.data());
+        for (size_t i = 0; i < count; ++i)
+          u[i] = es == 8 ? static_cast<double*>(out)[i] : (double)static_cast<float*>(out)[i];
+        const double err = (rc || orc) ? INFINITY : rel_linf(u, ref);
+        const double tol = prec == FM_F64 ? 1e-12 : 1e-5;
+        const bool ok = err <= tol;
+        failures += !ok;
+        std::printf("%s vector %d symmetric axes kind %d layout %d: status %d rel_linf %.3e %s\n",
+                    prec == FM_F64 ? "FP64" : "FP32", nsym, kind, layout, rc, err, ok ? "ok" : "FAIL");
+        std::free(rhs);
+        std::free(out);
+        fm_plan_destroy(plan);
+      }
   std::printf("emulated cases done, %d failure(s)\n", failures);
   return failures ? 1 : 0;
 }

@@ -10,7 +10,9 @@ the default tiling, in every launch mode its passes accept, and with fm_solve_st
 and compared with the FP64 oracle (FP64 1e-12, FP32 1e-5 relative L-infinity); then each
 precision's twelve in one fm_solve_batched call, compared bitwise with the single
 solves.  Also the 12 x 10 x 9 cell grid with faces EU / EU / EE in both precisions and
-two more FP32 grids, which join their precision's batch."""
+two more FP32 grids, which join their precision's batch; and Biot-Savart plans with
+faces per component on one, two and three symmetric axes (8 x 6 x 8, both layouts and
+precisions, the spectral curl and FD4), against the oracle's vector solve."""
 import os
 import shutil
 import subprocess
@@ -56,6 +58,7 @@ def test_device_code_under_cpu_emulation(tmp_path):
     # the one-launch batches ran and every precision reached the per-wavefront kernels
     for prec, count in (("FP32", 15), ("FP64", 13)):
         assert f"{prec} batched: {count} plans, status 0, {count} bitwise equal" in out
+    assert out.count(" vector ") == 12
     for prec in ("FP32", "FP64"):
         for mode in (1, 3, 4):
             assert f"{prec} mode {mode}" in out or (prec, mode) == ("FP64", 1)
