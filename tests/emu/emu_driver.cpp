@@ -4,7 +4,10 @@
 // the single solves.  Each case is also solved in every launch mode its passes accept
 // (fm_plan_set_tiling) and with fm_solve_static, on a stream of its own.  Finally
 // Biot-Savart plans with faces per component (one, two and three symmetric axes, the
-// spectral and a finite-difference curl) against the oracle's vector solve.  Cases come from a text file, one per line:
+// spectral and a finite-difference curl) against the oracle's vector solve; and every
+// case twice through a server (fm_server_*: three slots, a plan budget that forces
+// evictions) with its right-hand side copied from pinned memory on a producer stream
+// the server must wait for.  Cases come from a text file, one per line:
 //   prec nx ny nz hx hy hz bx0 bx1 by0 by1 bz0 bz1 layout seed
 // Prints one line per case and exits non-zero on any failure.
 #include <cmath>
@@ -42,6 +45,7 @@ void fill(std::vector<double>& v, unsigned seed) {
 double rel_linf(const std::vector<double>& a, const std::vector<double>& ref) {
   double num = 0, den = 0;
   for (size_t i = 0; i < a.size(); ++i) {
+    if (!std::isfinite(a[i])) return INFINITY;  // a NaN from uninitialised memory fails
     num = std::fmax(num, std::fabs(a[i] - ref[i]));
     den = std::fmax(den, std::fabs(ref[i]));
   }
@@ -241,6 +245,76 @@ int main(int argc, char** argv) {
         std::free(out);
         fm_plan_destroy(plan);
       }
+  // serving: the producer stream is created before the server's streams, so that the
+  // scheduler would run an unordered solve before the copy that fills its input
+  {
+    hipStream_t prod = nullptr;
+    hipStreamCreateWithFlags(&prod, hipStreamNonBlocking);
+    fm_server srv = nullptr;
+    int rc = fm_server_create(&srv, (size_t)64 << 20, (size_t)1 << 20, 3, 0);
+    struct Req {
+      const Case* k;
+      void *pin, *rhs, *out;
+      size_t count, es;
+      std::vector<double> ref;
+    };
+    std::vector<Req> reqs;
+    for (int rep = 0; rep < 2 && !rc; ++rep)
+      for (const Case& k : cases) {
+        Req q{&k, nullptr, nullptr, nullptr, 1, k.prec == FM_F64 ? 8u : 4u, {}};
+        for (int a = 0; a < 3; ++a) q.count *= (size_t)(k.n[a] + (k.layout == FM_NODE ? 1 : 0));
+        std::vector<double> f(q.count);
+        fill(f, k.seed + 1000);
+        hipHostMalloc(&q.pin, q.count * q.es, 0);
+        for (size_t i = 0; i < q.count; ++i) {
+          if (q.es == 8) static_cast<double*>(q.pin)[i] = f[i];
+          else {
+            static_cast<float*>(q.pin)[i] = (float)f[i];
+            f[i] = (double)static_cast<float*>(q.pin)[i];
+          }
+        }
+        q.rhs = std::malloc(q.count * q.es);
+        q.out = std::malloc(q.count * q.es);
+        std::memset(q.rhs, 0xff, q.count * q.es);
+        q.ref.resize(q.count);
+        oracle_solve(k.n, k.h, &k.bc[0][0], k.layout, 0, 0, 0, f.data(), q.ref.data());
+        hipMemcpyAsync(q.rhs, q.pin, q.count * q.es, hipMemcpyHostToDevice, prod);
+        long long ticket = 0;
+        const int sr = fm_server_submit(srv, k.n, k.h, k.bc, k.layout, FM_GREEN_CHAT2, k.prec, FM_POISSON, 1,
+                                        q.rhs, q.out, prod, &ticket);
+        if (sr) {
+          std::printf("serving submit failed: %s\n", fm_error_string(sr));
+          ++failures;
+        }
+        reqs.push_back(std::move(q));
+        // the second round reuses the cached plans: nothing in its submissions waits for
+        // the device, so its copies are still queued when its solves are admitted
+        if (&k == &cases.back() && rep == 0) rc = fm_server_wait_all(srv);
+      }
+    if (!rc) rc = fm_server_wait_all(srv);
+    fm_server_stats stats{};
+    if (!rc) rc = fm_server_get_stats(srv, &stats);
+    int good = 0;
+    for (Req& q : reqs) {
+      std::vector<double> u(q.count);
+      for (size_t i = 0; i < q.count; ++i)
+        u[i] = q.es == 8 ? static_cast<double*>(q.out)[i] : (double)static_cast<float*>(q.out)[i];
+      good += !rc && rel_linf(u, q.ref) <= (q.es == 8 ? 1e-12 : 1e-5);
+    }
+    const bool ok = !rc && good == (int)reqs.size() && stats.failed == 0;
+    failures += !ok;
+    std::printf("serving: %d requests, status %d, %d within tolerance, %lld plan hits, %lld evictions, "
+                "peak in flight %d, failed %lld %s\n",
+                (int)reqs.size(), rc, good, stats.plan_hits, stats.plan_evictions, stats.peak_inflight,
+                stats.failed, ok ? "ok" : "FAIL");
+    if (srv) fm_server_destroy(srv);
+    for (Req& q : reqs) {
+      hipHostFree(q.pin);
+      std::free(q.rhs);
+      std::free(q.out);
+    }
+    hipStreamDestroy(prod);
+  }
   std::printf("emulated cases done, %d failure(s)\n", failures);
   return failures ? 1 : 0;
 }

@@ -12,7 +12,10 @@ precision's twelve in one fm_solve_batched call, compared bitwise with the singl
 solves.  Also the 12 x 10 x 9 cell grid with faces EU / EU / EE in both precisions and
 two more FP32 grids, which join their precision's batch; and Biot-Savart plans with
 faces per component on one, two and three symmetric axes (8 x 6 x 8, both layouts and
-precisions, the spectral curl and FD4), against the oracle's vector solve."""
+precisions, the spectral curl and FD4), against the oracle's vector solve; and every
+case twice through a server (three slots), its right-hand side copied from pinned memory
+on a producer stream created before the server's, so that a solve not ordered after
+that copy would read the NaN-filled input."""
 import os
 import shutil
 import subprocess
@@ -59,6 +62,7 @@ def test_device_code_under_cpu_emulation(tmp_path):
     for prec, count in (("FP32", 15), ("FP64", 13)):
         assert f"{prec} batched: {count} plans, status 0, {count} bitwise equal" in out
     assert out.count(" vector ") == 12
+    assert "serving: 56 requests, status 0, 56 within tolerance" in out
     for prec in ("FP32", "FP64"):
         for mode in (1, 3, 4):
             assert f"{prec} mode {mode}" in out or (prec, mode) == ("FP64", 1)
