@@ -9,7 +9,8 @@ Replayed: the twelve FP32 and twelve FP64 plans of the batched-equals-single GPU
 the default tiling, in every launch mode its passes accept, and with fm_solve_static,
 and compared with the FP64 oracle (FP64 1e-12, FP32 1e-5 relative L-infinity); then each
 precision's twelve in one fm_solve_batched call, compared bitwise with the single
-solves.  Also the 12 x 10 x 9 cell grid with faces EU / EU / EE in both precisions and
+solves.  Also the 12 x 10 x 9 cell grid with faces EU / EU / EE in both precisions (also
+as its passes one call at a time with the second repeated, and as a one-plan batch) and
 two more FP32 grids, which join their precision's batch; and Biot-Savart plans with
 faces per component on one, two and three symmetric axes (8 x 6 x 8, both layouts and
 precisions, the spectral curl and FD4), against the oracle's vector solve; and every
@@ -62,6 +63,7 @@ def test_device_code_under_cpu_emulation(tmp_path):
     for prec, count in (("FP32", 15), ("FP64", 13)):
         assert f"{prec} batched: {count} plans, status 0, {count} bitwise equal" in out
     assert out.count(" vector ") == 12
+    assert out.count("status 0 bitwise equal, one-plan batch status 0 bitwise equal") == 2
     assert "serving: 56 requests, status 0, 56 within tolerance" in out
     for prec in ("FP32", "FP64"):
         for mode in (1, 3, 4):
