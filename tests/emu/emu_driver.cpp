@@ -316,7 +316,7 @@ int main(int argc, char** argv) {
           ++failures;
         }
         reqs.push_back(std::move(q));
-        // the second round reuses the cached plans: nothing in its submissions waits for
+        // the second sweep reuses the cached plans: nothing in its submissions waits for
         // the device, so its copies are still queued when its solves are admitted
         if (&k == &cases.back() && rep == 0) rc = fm_server_wait_all(srv);
       }
